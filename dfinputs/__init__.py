@@ -1,0 +1,103 @@
+"""Seeded synthetic inputs for the DF J/K build.
+
+This module only draws and shapes input data; it holds none of the build's
+arithmetic, and both the HIP library's tests/benchmarks and the CPU oracle's
+tests consume exactly the bytes it produces.
+
+Recipe (shapes and structure follow the paper's 6-311G(d,p) workloads:
+naux / nao ~ 4, nocc / nao ~ 1/6 .. 1/8; Table 3):
+
+* G[P, mu, nu] ~ N(0, 1);
+  B = G * exp(-|mu - nu| / L) * exp(-P / naux)  (basis-function locality and a
+  decaying aux spectrum), then B_P <- (B_P + B_P^T) / 2;
+* optional per-aux-row scale r_P = 10^U(-6, 0) applied after symmetrisation
+  (the wide dynamic range of whitened B);
+* C = Q of the reduced QR of an N(0, 1) nao x nocc matrix (orthonormal
+  occupied orbitals), D = occ * C C^T (closed shell, occ = 2).
+
+``make_problem`` draws everything from ``numpy.random.default_rng(seed)`` in
+the order G, M (for C), r.  ``make_problem_device`` draws G on the GPU with
+torch's seeded device generator, in aux chunks, for sizes the host should not
+build; C, D and r still come from the NumPy stream.  The two streams differ:
+device-built tensors are checked by copying slabs back, never by regenerating.
+"""
+import numpy as np
+
+CONFIG0 = dict(nao=96, naux=384, nocc=16, L=12.0, row_scale=False)
+CONFIG1 = dict(nao=768, naux=3072, nocc=96, L=24.0, row_scale=True)
+
+
+def _decay(nao, naux, L):
+    mu = np.arange(nao, dtype=np.float64)
+    dmn = np.exp(-np.abs(mu[:, None] - mu[None, :]) / L)
+    dp = np.exp(-np.arange(naux, dtype=np.float64) / naux)
+    return dmn, dp
+
+
+def make_orbitals(rng, nao, nocc, occ=2.0):
+    M = rng.standard_normal((nao, nocc))
+    C, _ = np.linalg.qr(M)
+    C = np.ascontiguousarray(C)
+    D = occ * (C @ C.T)
+    return C, D
+
+
+def make_problem(nao, naux, nocc, L=12.0, seed=0, row_scale=False, occ=2.0):
+    """Host-side problem: dict(B (naux, nao, nao), C, D, r, occ)."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((naux, nao, nao))
+    dmn, dp = _decay(nao, naux, L)
+    B = G * dmn[None, :, :] * dp[:, None, None]
+    B = 0.5 * (B + B.transpose(0, 2, 1))
+    C, D = make_orbitals(rng, nao, nocc, occ)
+    r = None
+    if row_scale:
+        r = 10.0 ** rng.uniform(-6.0, 0.0, naux)
+        B *= r[:, None, None]
+    return dict(B=np.ascontiguousarray(B), C=C, D=D, r=r, occ=occ)
+
+
+def config0(seed=0):
+    return make_problem(seed=seed, **CONFIG0)
+
+
+def make_problem_device(nao, naux, nocc, L=12.0, seed=0, row_scale=False, occ=2.0,
+                        device="cuda", chunk=128):
+    """Device-side problem (torch float64 tensors on ``device``).
+
+    G is drawn with ``torch.Generator(device).manual_seed(seed)`` one aux chunk
+    of ``chunk`` rows at a time; C, D and r come from the NumPy stream of
+    ``seed`` (M first, then r).
+    """
+    import torch
+    rng = np.random.default_rng(seed)
+    C, D = make_orbitals(rng, nao, nocc, occ)
+    r = 10.0 ** rng.uniform(-6.0, 0.0, naux) if row_scale else None
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    dmn, dp = _decay(nao, naux, L)
+    dmn_t = torch.from_numpy(dmn).to(device)
+    scale = dp if r is None else dp * r
+    B = torch.empty((naux, nao, nao), dtype=torch.float64, device=device)
+    for p0 in range(0, naux, chunk):
+        p1 = min(p0 + chunk, naux)
+        G = torch.randn((p1 - p0, nao, nao), generator=gen, dtype=torch.float64,
+                        device=device)
+        G.mul_(dmn_t)
+        G = 0.5 * (G + G.transpose(1, 2))
+        G.mul_(torch.from_numpy(scale[p0:p1]).to(device)[:, None, None])
+        B[p0:p1].copy_(G)
+        del G
+    return dict(B=B, C=torch.from_numpy(C).to(device), D=torch.from_numpy(D).to(device),
+                C_host=C, D_host=D, r=r, occ=occ)
+
+
+def random_problem(rng, nao, naux, nocc, L=None, occ=2.0):
+    """Small problem with a given Generator (for shape sweeps in tests)."""
+    L = float(nao) / 4 if L is None else L
+    G = rng.standard_normal((naux, nao, nao))
+    dmn, dp = _decay(nao, naux, L)
+    B = G * dmn[None] * dp[:, None, None]
+    B = 0.5 * (B + B.transpose(0, 2, 1))
+    C, D = make_orbitals(rng, nao, nocc, occ)
+    return dict(B=np.ascontiguousarray(B), C=C, D=D, r=None, occ=occ)
