@@ -20,7 +20,8 @@ from the arithmetic:
   4 - 8 g), in FP64 with round-to-nearest-even, smallest weight first.
 * The K pipeline (Eqs. df-k-blk-1/2): X_b = emu(B_b, C) for each block of
   ``pblk`` consecutive aux indices, X_b sliced per row mu over (P in b, i),
-  K_b = emu(X_b X_b^T), K = occ * sum_b K_b with b ascending.
+  K_b = emu(X_b X_b^T), K = occ * sum_b K_b with b ascending (optionally
+  inside contiguous groups of blocks whose sums are then added in order).
 
 Pins (tests/test_oracle_emulation.py): digit bounds, prefix property, exact
 level-8 reconstruction of N (Python integers); the slicing error bound;
@@ -241,9 +242,18 @@ def x_block(X, p0, p1):
     return np.ascontiguousarray(X[p0:p1].transpose(1, 0, 2)).reshape(nao, (p1 - p0) * nocc)
 
 
-def emulated_k(X, s, occ=2.0, pblk=64):
-    """Eq. (6) blocked and emulated: K = occ * sum_b emu(X_b X_b^T), b ascending.
+def block_groups(nb, groups):
+    """Contiguous groups of aux blocks: group g holds blocks [g nb / G, (g+1) nb / G)."""
+    groups = max(1, min(groups, nb))
+    return [(g * nb // groups, (g + 1) * nb // groups) for g in range(groups)]
 
+
+def emulated_k(X, s, occ=2.0, pblk=64, groups=1):
+    """Eq. (6) blocked and emulated: K = occ * sum_b emu(X_b X_b^T).
+
+    The block partial sums are added in ascending order inside ``groups``
+    contiguous groups of blocks, and the group sums in ascending order
+    (groups = 1 is the plain ascending sum over b).
     Returns (K, F[nblocks, nao]) with F the per-(block, mu) slicing exponents.
     For s == 0 each K_b is the FP64 product X_b X_b^T.
     """
@@ -251,18 +261,22 @@ def emulated_k(X, s, occ=2.0, pblk=64):
     blocks = block_ranges(naux, pblk)
     if s and not int32_guard_ok(pblk * nocc, s):
         raise OverflowError("pblk * nocc exceeds the int32 guard at this slice count")
-    Kacc = np.zeros((nao, nao))
     F = np.zeros((len(blocks), nao), dtype=np.int64)
-    for bi, (p0, p1) in enumerate(blocks):
-        Xb = x_block(X, p0, p1)
-        F[bi] = row_exponents(Xb)
-        if s == 0:
-            Kb = Xb @ Xb.T
-        else:
-            dX, _ = slice_rows(Xb, s)
-            S = slice_products(dX, dX.transpose(0, 2, 1), s)
-            Kb = recombine(S, F[bi], F[bi], s)
-        Kacc = Kacc + Kb
+    Kacc = np.zeros((nao, nao))
+    for g0, g1 in block_groups(len(blocks), groups):
+        Kg = np.zeros((nao, nao))
+        for bi in range(g0, g1):
+            p0, p1 = blocks[bi]
+            Xb = x_block(X, p0, p1)
+            F[bi] = row_exponents(Xb)
+            if s == 0:
+                Kb = Xb @ Xb.T
+            else:
+                dX, _ = slice_rows(Xb, s)
+                S = slice_products(dX, dX.transpose(0, 2, 1), s)
+                Kb = recombine(S, F[bi], F[bi], s)
+            Kg = Kg + Kb
+        Kacc = Kacc + Kg
     return occ * Kacc, F
 
 
@@ -307,7 +321,7 @@ def k_error_bound(e_B, f_C, F, s, occ=2.0, pblk=64, nocc=None):
     return bound
 
 
-def emulated_build_jk(B, C, s, occ=2.0, D=None, pblk=64):
+def emulated_build_jk(B, C, s, occ=2.0, D=None, pblk=64, groups=1):
     """The emulated build: rho and J in FP64 (Eqs. 3-4), X and K emulated.
 
     Returns dict(rho, J, X, K, e_j, e_x, D, e_B, f_C, F, bound) where
@@ -321,7 +335,7 @@ def emulated_build_jk(B, C, s, occ=2.0, D=None, pblk=64):
     rho = _jk.rho_of(B, D)
     J = _jk.j_of(B, rho)
     X, e_B, f_C = emulated_x(B, C, s)
-    K, F = emulated_k(X, s, occ=occ, pblk=pblk)
+    K, F = emulated_k(X, s, occ=occ, pblk=pblk, groups=groups)
     e_j, e_x = _jk.energies(rho, D, K)
     bound = k_error_bound(e_B, f_C, F, s, occ=occ, pblk=pblk) if s else None
     return dict(rho=rho, J=J, X=X, K=K, e_j=e_j, e_x=e_x, D=D,

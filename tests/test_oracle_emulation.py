@@ -235,3 +235,16 @@ def test_subset_restriction_is_exact(prob):
     X, _, _ = em.emulated_x(prob["B"][:, S, :], prob["C"], s)
     Ks, _ = em.emulated_k(X, s)
     assert np.array_equal(Ks, full["K"][np.ix_(S, S)])
+
+
+def test_block_groups_partition_and_order(prob):
+    from oracle.emulation import block_groups
+    assert block_groups(6, 4) == [(0, 1), (1, 3), (3, 4), (4, 6)]
+    assert block_groups(3, 8) == [(0, 1), (1, 2), (2, 3)]
+    a = em.emulated_build_jk(prob["B"], prob["C"], 4, pblk=16, groups=1)
+    b = em.emulated_build_jk(prob["B"], prob["C"], 4, pblk=16, groups=3)
+    # same per-block products, only the FP64 summation order differs
+    ref = jk.build_jk(prob["B"], prob["C"])["K"]
+    assert np.all(np.abs(b["K"] - ref) <= b["bound"])
+    assert np.abs(a["K"] - b["K"]).max() <= 16 * 2.0 ** -53 * np.abs(a["K"]).max()
+    assert np.array_equal(b["K"], b["K"].T)
