@@ -1,0 +1,151 @@
+/*
+ * dfjk.h -- C ABI of the MI355X (gfx950) density-fitting Coulomb/exchange build.
+ *
+ * The library computes, for a whitened three-index tensor B[P][mu][nu]
+ * (naux x nao x nao, symmetric in mu, nu), occupied orbitals C[nu][i]
+ * (nao x nocc) and the density D = occ * C C^T:
+ *
+ *   rho_P      = sum_{mu,nu} B[P][mu][nu] D[mu][nu]          (Sec. 2.1, Eq. 3)
+ *   J[mu][nu]  = sum_P rho_P B[P][mu][nu]                     (Eq. 4)
+ *   X[P][mu][i]= sum_nu B[P][mu][nu] C[nu][i]                 (Eq. 5; the paper's W)
+ *   K[mu][nu]  = occ * sum_{P,i} X[P][mu][i] X[P][nu][i]      (Eq. 6)
+ *   E_J = 1/2 sum_P rho_P^2,   E_x = -1/4 sum_{mu,nu} D K
+ *
+ * K is formed per block of `pblk` consecutive aux indices (Eqs. df-k-blk-1/2
+ * of Sec. 3.3).  Its two products run either in native FP64 (slices = 0) or
+ * as FP64 emulated by s = 1..8 INT8 slices (Sec. 3.2: s = ceil((m + 1) / 8)
+ * splits for m mantissa bits):
+ *   - every operand row r (over the contraction index) gets the power-of-two
+ *     exponent e_r of its largest magnitude; trunc(a * 2^(62 - e_r)) is split
+ *     into balanced base-256 digits d_1..d_8 (d_1 most significant), of which
+ *     a level-s slicing keeps d_1..d_s;
+ *   - the s(s+1)/2 digit products with a + b <= s + 1 are accumulated exactly
+ *     in int32, one accumulator per anti-diagonal g = a + b;
+ *   - FP64 recombination: Z = sum_{g = s+1 .. 2} ldexp(S_g, e_r + f_c + 4 - 8g),
+ *     smallest weight first.
+ * J and rho are FP64 in both modes (Sec. 3, first bullet: J stays FP64).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers to caller-owned memory (allocated by
+ *     the caller, e.g. through PyTorch).  The library never frees or keeps them
+ *     after the call returns.  Arrays are row-major and C-contiguous; double
+ *     arrays must be 8-byte aligned, int8 arrays 16-byte aligned.
+ *   - Work is enqueued asynchronously on the context's HIP stream; outputs are
+ *     valid after that stream is synchronised.
+ *   - Return value: DF_OK (0) or a negative DF_E* code.  Argument errors are
+ *     reported synchronously and enqueue nothing; df_last_error() gives text.
+ *     Data errors found on the device (a NaN or Inf in a sliced operand) set
+ *     a status word that df_get_status() reads (it synchronises the stream).
+ *   - One context per stream; a context is not thread-safe.
+ */
+#ifndef DFJK_H
+#define DFJK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum df_status {
+  DF_OK = 0,
+  DF_EINVAL = -1,          /* bad shape, pointer, slice count or layout          */
+  DF_EWORKSPACE = -2,      /* workspace missing or smaller than df_workspace_size */
+  DF_EHIP = -3,            /* a HIP runtime call failed                          */
+  DF_ENONFINITE = -4,      /* NaN/Inf met while slicing (device status)          */
+  DF_EOVERFLOW_GUARD = -5  /* s * pblk * nocc * 2^14 >= 2^31: int32 sums unsafe  */
+};
+
+enum df_layout {
+  DF_DENSE = 0             /* B as [naux][nao][nao]                               */
+};
+
+typedef struct df_ctx df_ctx;
+
+/* Create a context bound to `hip_stream` (a hipStream_t; NULL = null stream).
+ * Precision starts at 0 (native FP64), the aux block size at 64. */
+int df_create(df_ctx** ctx, void* hip_stream);
+
+/* Destroy a context (does not touch caller memory).  NULL is ignored. */
+void df_destroy(df_ctx* ctx);
+
+/* Slice count used by df_build_jk / df_build_x: 0 = native FP64 MFMA,
+ * 1..8 = INT8 slices (Table 1 of the paper uses 3..6).  DF_EINVAL otherwise. */
+int df_set_precision(df_ctx* ctx, int slices);
+int df_get_precision(const df_ctx* ctx);
+
+/* Aux block size of the blocked K (Eqs. df-k-blk-1/2): 1..1024 (default 64). */
+int df_set_pblk(df_ctx* ctx, int pblk);
+
+/* Number of contiguous groups of aux blocks whose exchange partial sums are
+ * formed independently and then added in ascending group order (0 = let the
+ * library choose from the problem shape; the value used by the last build is
+ * returned by df_get_k_groups).  Within a group the blocks are added in
+ * ascending order, so the emulated K is deterministic for a given value. */
+int df_set_k_groups(df_ctx* ctx, int groups);
+int df_get_k_groups(const df_ctx* ctx);
+
+/* Bytes of device workspace needed by df_build_jk / df_build_x for this shape
+ * at any precision.  The caller allocates it and hands it over with
+ * df_set_workspace (the library only borrows it until the next call). */
+int df_workspace_size(df_ctx* ctx, int64_t naux, int64_t nao, int64_t nocc, int layout,
+                      size_t* bytes);
+int df_set_workspace(df_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Row exponents of B over nu: b_exp[P*nao + mu] = e with
+ * 2^(e-1) <= max_nu |B[P][mu][nu]| < 2^e (0 for an all-zero row).
+ * B does not change across SCF iterations, so callers compute this once and
+ * pass it to every df_build_jk / df_build_x call.  Non-finite B sets the
+ * DF_ENONFINITE device status. */
+int df_b_exponents(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t nao,
+                   int32_t* b_exp);
+
+/* Slice the rows of A (rows x cols, leading dimension lda >= cols) at level
+ * `slices` (1..8): digits[a][r][c] (int8, a = 0 is the most significant
+ * digit d_1) and row_exp[r] as defined above.  Sec. 3.2 / Sec. 2.3, Eq. 8. */
+int df_slice(df_ctx* ctx, const double* A, int64_t rows, int64_t cols, int64_t lda,
+             int slices, int8_t* digits, int32_t* row_exp);
+
+/* Eq. (5) alone at the context precision: X[P][mu][i] (naux x nao x nocc).
+ * b_exp may be NULL (it is then computed into the workspace). */
+int df_build_x(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t nao,
+               const int32_t* b_exp, const double* C, int64_t nocc, double* X);
+
+/* The whole build at the context precision (Eqs. 3-6).
+ *   B       [naux][nao][nao] (layout DF_DENSE), symmetric in the last two indices
+ *   b_exp   [naux*nao] from df_b_exponents, or NULL
+ *   C       [nao][nocc];  occ the occupation factor (2 for closed shells)
+ *   D       [nao][nao], the density occ * C C^T used for rho
+ *   J, K    [nao][nao] outputs (both written in full, symmetric)
+ *   energies[2] output: E_J, E_x
+ *   err_bound[1] output: an upper bound on max |K - K_exact| (absolute) that
+ *           covers the slicing, the dropped digit pairs and FP64 rounding of
+ *           the emulated products (s >= 1), or the FP64 dot-product bound (s = 0).
+ * Requires a workspace of df_workspace_size bytes. */
+int df_build_jk(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t nao,
+                const int32_t* b_exp, const double* C, int64_t nocc, double occ,
+                const double* D, double* J, double* K, double* energies, double* err_bound);
+
+/* Device status word (0 or DF_ENONFINITE) accumulated since the last call;
+ * synchronises the context stream and clears the word. */
+int df_get_status(df_ctx* ctx);
+
+/* Text of the last synchronous error of this context ("" if none). */
+const char* df_last_error(const df_ctx* ctx);
+
+/* Test hook: the exact int32 products of every kept slice pair, as formed by
+ * the INT8 MFMA tiles of the emulated products.  a_dig [s][m][k] and
+ * b_dig [s][k][n] are int8 digit planes; partials[p][m][n] receives
+ * sum_k a_dig[a-1][.][k] * b_dig[b-1][k][.] for the p-th pair (a, b) in the
+ * order a = 1..s, b = 1..s+1-a.  Needs k <= 131072 (single-pair int32 range)
+ * and a workspace of at least s*M*Kp (rounded up to 256) + s*N*Kp bytes, with
+ * M, N, Kp = m, n, k rounded up to multiples of 64. */
+int df_debug_slice_gemm_i32(df_ctx* ctx, const int8_t* a_dig, const int8_t* b_dig, int64_t m,
+                            int64_t n, int64_t k, int s, int32_t* partials);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DFJK_H */

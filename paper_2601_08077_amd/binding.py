@@ -1,0 +1,171 @@
+"""ctypes binding of libdfjk.so: the C ABI of include/dfjk.h, same names.
+
+Argument marshalling only: torch tensors provide device pointers and the HIP
+stream; every step of the build runs in the library's kernels.  Importing
+works without a GPU; loading the library fails loudly if it was not built.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdfjk.so")
+
+DF_OK, DF_EINVAL, DF_EWORKSPACE, DF_EHIP, DF_ENONFINITE, DF_EOVERFLOW_GUARD = 0, -1, -2, -3, -4, -5
+DF_DENSE = 0
+
+_c_void_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "df_create": (_int, [ctypes.POINTER(_c_void_p), _c_void_p]),
+    "df_destroy": (None, [_c_void_p]),
+    "df_set_precision": (_int, [_c_void_p, _int]),
+    "df_get_precision": (_int, [_c_void_p]),
+    "df_set_pblk": (_int, [_c_void_p, _int]),
+    "df_set_k_groups": (_int, [_c_void_p, _int]),
+    "df_get_k_groups": (_int, [_c_void_p]),
+    "df_workspace_size": (_int, [_c_void_p, _i64, _i64, _i64, _int, ctypes.POINTER(ctypes.c_size_t)]),
+    "df_set_workspace": (_int, [_c_void_p, _c_void_p, ctypes.c_size_t]),
+    "df_b_exponents": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _c_void_p]),
+    "df_slice": (_int, [_c_void_p, _c_void_p, _i64, _i64, _i64, _int, _c_void_p, _c_void_p]),
+    "df_build_x": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _c_void_p, _c_void_p, _i64,
+                          _c_void_p]),
+    "df_build_jk": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _c_void_p, _c_void_p, _i64,
+                           ctypes.c_double, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "df_get_status": (_int, [_c_void_p]),
+    "df_last_error": (ctypes.c_char_p, [_c_void_p]),
+    "df_debug_slice_gemm_i32": (_int, [_c_void_p, _c_void_p, _c_void_p, _i64, _i64, _i64, _int,
+                                       _c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libdfjk.so (once) and declare every exported signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2601_08077_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class DFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A df_ctx bound to a torch CUDA(HIP) stream, plus its workspace tensor."""
+
+    def __init__(self, stream=None):
+        import torch
+        self.lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.df_create(ctypes.byref(h), ctypes.c_void_p(stream.cuda_stream))
+        if rc != DF_OK:
+            raise DFError(rc, "df_create failed")
+        self.h = h
+        self.ws = None
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.df_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != DF_OK:
+            msg = self.lib.df_last_error(self.h)
+            raise DFError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    # -- configuration --------------------------------------------------------
+    def df_set_precision(self, slices):
+        self._check(self.lib.df_set_precision(self.h, int(slices)), "df_set_precision")
+
+    def df_get_precision(self):
+        return self.lib.df_get_precision(self.h)
+
+    def df_set_pblk(self, pblk):
+        self._check(self.lib.df_set_pblk(self.h, int(pblk)), "df_set_pblk")
+
+    def df_set_k_groups(self, groups):
+        self._check(self.lib.df_set_k_groups(self.h, int(groups)), "df_set_k_groups")
+
+    def df_get_k_groups(self):
+        return self.lib.df_get_k_groups(self.h)
+
+    def df_workspace_size(self, naux, nao, nocc, layout=DF_DENSE):
+        n = ctypes.c_size_t()
+        self._check(self.lib.df_workspace_size(self.h, naux, nao, nocc, layout, ctypes.byref(n)),
+                    "df_workspace_size")
+        return n.value
+
+    def df_set_workspace(self, ws):
+        """Hand over a uint8 device tensor (kept alive by this object)."""
+        self.ws = ws
+        self._check(self.lib.df_set_workspace(self.h, _ptr(ws), 0 if ws is None else ws.numel()),
+                    "df_set_workspace")
+
+    def ensure_workspace(self, naux, nao, nocc, layout=DF_DENSE):
+        import torch
+        need = self.df_workspace_size(naux, nao, nocc, layout)
+        if self.ws is None or self.ws.numel() < need:
+            self.df_set_workspace(None)
+            self.df_set_workspace(torch.empty(need, dtype=torch.uint8, device="cuda"))
+        return need
+
+    # -- compute entry points -------------------------------------------------
+    def df_b_exponents(self, B, b_exp, layout=DF_DENSE):
+        naux, nao = B.shape[0], B.shape[1]
+        self._check(self.lib.df_b_exponents(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp)),
+                    "df_b_exponents")
+
+    def df_slice(self, A, slices, digits, row_exp):
+        rows, cols = A.shape
+        self._check(self.lib.df_slice(self.h, _ptr(A), rows, cols, A.stride(0), int(slices),
+                                      _ptr(digits), _ptr(row_exp)), "df_slice")
+
+    def df_build_x(self, B, b_exp, C, X, layout=DF_DENSE):
+        naux, nao = B.shape[0], B.shape[1]
+        self._check(self.lib.df_build_x(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp), _ptr(C),
+                                        C.shape[1], _ptr(X)), "df_build_x")
+
+    def df_build_jk(self, B, b_exp, C, occ, D, J, K, energies, err_bound, layout=DF_DENSE):
+        naux, nao = B.shape[0], B.shape[1]
+        self._check(self.lib.df_build_jk(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp), _ptr(C),
+                                         C.shape[1], float(occ), _ptr(D), _ptr(J), _ptr(K),
+                                         _ptr(energies), _ptr(err_bound)), "df_build_jk")
+
+    def df_get_status(self):
+        return self.lib.df_get_status(self.h)
+
+    def df_debug_slice_gemm_i32(self, a_dig, b_dig, s, partials):
+        _, m, k = a_dig.shape
+        n = b_dig.shape[2]
+        self._check(self.lib.df_debug_slice_gemm_i32(self.h, _ptr(a_dig), _ptr(b_dig), m, n, k,
+                                                     int(s), _ptr(partials)),
+                    "df_debug_slice_gemm_i32")

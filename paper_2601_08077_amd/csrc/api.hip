@@ -1,0 +1,375 @@
+// C ABI of libdfjk: argument checks, workspace carving and the launch sequence
+// of the density-fitting J/K build (Sec. 2.1 Eqs. 3-6, Sec. 3.2-3.3).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "../../include/dfjk.h"
+#include "dfjk_internal.h"
+
+struct df_ctx {
+  hipStream_t stream = nullptr;
+  int slices = 0;
+  int pblk = 64;
+  int k_groups_req = 0;
+  int k_groups_used = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int* status = nullptr;  // device word owned by the context
+  std::string err;
+};
+
+namespace {
+
+using namespace dfjk;
+
+int fail(df_ctx* c, int code, const char* msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(df_ctx* c, hipError_t e, const char* where) {
+  if (c) {
+    c->err = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return DF_EHIP;
+}
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Error-bound factor of one emulated product over k terms (slices s >= 1), or
+// the FP64 dot-product factor gamma_k (s == 0):
+//   |Z - Z_hat| <= k 2^(e_r + f_c) kappa.
+// s >= 1: slicing of both operands (2 eps + eps^2, eps the largest dropped
+// tail of a balanced base-256 expansion plus the 62-bit truncation), the digit
+// pairs with a + b >= s + 2 that are not formed (2s + 1 - g pairs of weight
+// 2^(18 - 8g) at each g), and the s - 1 FP64 roundings of the recombination.
+double kappa_of(int s, int64_t k) {
+  const double u = ldexp(1.0, -53);
+  if (s == 0) {
+    const double ku = (double)k * u;
+    return ku / (1.0 - ku);
+  }
+  const double eps = (128.0 / 255.0) * ldexp(1.0, 2 - 8 * s) * (1.0 - ldexp(1.0, -8 * (8 - s))) +
+                     ldexp(1.0, -62);
+  double dropped = 0.0;
+  for (int g = s + 2; g <= 2 * s; ++g) dropped += (double)(2 * s + 1 - g) * ldexp(1.0, 18 - 8 * g);
+  const double rounding = (s - 1) * u * 1.016 * pow(1.0 + u, (double)s);
+  return 2.0 * eps + eps * eps + dropped + rounding;
+}
+
+// Shape-derived sizes shared by the workspace query and the build.
+struct Plan {
+  int64_t naux, nao, nocc;
+  int pblk, nb, nao_pad, kbp, ncp, kp, groups, jsplit;
+  size_t off_bexp, off_fcol, off_dC, off_X, off_xmax, off_F, off_Xd, off_rho, off_Jp, off_Kp,
+      off_bsc, total;
+};
+
+size_t carve(size_t& cur, size_t bytes) {
+  const size_t o = cur;
+  cur += (bytes + 255) / 256 * 256;
+  return o;
+}
+
+Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
+  Plan p{};
+  p.naux = naux;
+  p.nao = nao;
+  p.nocc = nocc;
+  p.pblk = c->pblk;
+  p.nb = (int)((naux + p.pblk - 1) / p.pblk);
+  p.nao_pad = (int)round_up(nao, 64);
+  p.kbp = (int)round_up((int64_t)p.pblk * nocc, 64);
+  p.ncp = nocc <= 32 ? 32 : (nocc <= 64 ? 64 : (int)round_up(nocc, 96));
+  p.kp = (int)round_up(nao, 64);
+  const int nt = p.nao_pad / 64;
+  const int tiles = nt * (nt + 1) / 2;
+  int g = c->k_groups_req;
+  if (g <= 0) g = (int)std::min<int64_t>(std::max<int64_t>(1, (1024 + tiles - 1) / tiles), 64);
+  p.groups = std::max(1, std::min(g, p.nb));
+  const int64_t nn = nao * nao;
+  const int64_t nch = (nn + 511) / 512;
+  p.jsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, 2048 / std::max<int64_t>(nch, 1)));
+  p.jsplit = (int)std::min<int64_t>(p.jsplit, std::max<int64_t>(naux, 1));
+  size_t cur = 0;
+  p.off_bexp = carve(cur, (size_t)naux * nao * 4);
+  p.off_fcol = carve(cur, (size_t)std::max<int64_t>(nocc, 1) * 4);
+  p.off_dC = carve(cur, (size_t)kMaxSlices * p.ncp * p.kp);
+  p.off_X = carve(cur, (size_t)naux * nao * nocc * 8);
+  p.off_xmax = carve(cur, (size_t)p.nb * nao * 8);
+  p.off_F = carve(cur, (size_t)p.nb * p.nao_pad * 4);
+  p.off_Xd = carve(cur, (size_t)kMaxSlices * p.nb * p.nao_pad * p.kbp);
+  p.off_rho = carve(cur, (size_t)naux * 8);
+  p.off_Jp = carve(cur, (size_t)(p.jsplit > 1 ? p.jsplit : 0) * nn * 8);
+  p.off_Kp = carve(cur, (size_t)p.groups * nn * 8);
+  p.off_bsc = carve(cur, (size_t)p.nb * nao * 3 * 8);
+  p.total = cur;
+  return p;
+}
+
+int check_shape(df_ctx* c, int layout, int64_t naux, int64_t nao, int64_t nocc) {
+  if (!c) return DF_EINVAL;
+  if (layout != DF_DENSE) return fail(c, DF_EINVAL, "layout: only DF_DENSE is supported");
+  if (naux < 1 || nao < 1 || nocc < 1) return fail(c, DF_EINVAL, "naux, nao and nocc must be >= 1");
+  if (nao > 65536 || nocc > 65536 || naux > (int64_t)1 << 31)
+    return fail(c, DF_EINVAL, "dimension too large");
+  if (nocc > nao) return fail(c, DF_EINVAL, "nocc must not exceed nao");
+  return DF_OK;
+}
+
+int check_guard(df_ctx* c, int s, int64_t nao, int64_t nocc) {
+  if (s == 0) return DF_OK;
+  const double lim = 2147483648.0;
+  if ((double)s * (double)c->pblk * (double)nocc * 16384.0 >= lim)
+    return fail(c, DF_EOVERFLOW_GUARD, "s * pblk * nocc * 2^14 >= 2^31: lower pblk");
+  if ((double)s * (double)nao * 16384.0 >= lim)
+    return fail(c, DF_EOVERFLOW_GUARD, "s * nao * 2^14 >= 2^31");
+  return DF_OK;
+}
+
+template <class T>
+T* at(df_ctx* c, size_t off) {
+  return reinterpret_cast<T*>(c->ws + off);
+}
+
+#define DF_HIP(call, where)                       \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(c, e_, where); \
+  } while (0)
+
+// X (and the per-(block, mu) max of |X|) at the context precision.
+int run_x(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp, const double* C,
+          double* X) {
+  const int s = c->slices;
+  unsigned long long* xmax = at<unsigned long long>(c, p.off_xmax);
+  DF_HIP(launch_fill_u64(c->stream, xmax, (int64_t)p.nb * p.nao, 0ull), "fill xmax");
+  if (s == 0) {
+    DF_HIP(launch_x_fp64(c->stream, B, p.naux, (int)p.nao, C, (int)p.nocc, X, xmax, p.pblk),
+           "x_fp64");
+    return DF_OK;
+  }
+  int32_t* fcol = at<int32_t>(c, p.off_fcol);
+  int8_t* dC = at<int8_t>(c, p.off_dC);
+  DF_HIP(launch_col_exp(c->stream, C, p.nao, p.nocc, fcol, c->status), "col_exp");
+  DF_HIP(launch_slice_c(c->stream, C, p.nao, p.nocc, s, fcol, p.ncp, p.kp, dC), "slice_c");
+  DF_HIP(launch_x_int8(c->stream, s, B, p.naux, (int)p.nao, b_exp, dC, p.ncp, p.kp, fcol,
+                       (int)p.nocc, X, xmax, p.pblk),
+         "x_int8");
+  return DF_OK;
+}
+
+int common_checks(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao,
+                  const double* C, int64_t nocc, Plan& p) {
+  int rc = check_shape(c, layout, naux, nao, nocc);
+  if (rc) return rc;
+  if (!B || !C) return fail(c, DF_EINVAL, "null B or C");
+  rc = check_guard(c, c->slices, nao, nocc);
+  if (rc) return rc;
+  p = make_plan(c, naux, nao, nocc);
+  if (!c->ws || c->ws_bytes < p.total) return fail(c, DF_EWORKSPACE, "workspace too small");
+  return DF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int df_create(df_ctx** ctx, void* hip_stream) {
+  if (!ctx) return DF_EINVAL;
+  *ctx = nullptr;
+  df_ctx* c = new df_ctx();
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipMalloc(&c->status, 256);
+  if (e != hipSuccess) {
+    delete c;
+    return DF_EHIP;
+  }
+  e = launch_fill_i32(c->stream, c->status, 1, 0);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(c->status);
+    delete c;
+    return DF_EHIP;
+  }
+  *ctx = c;
+  return DF_OK;
+}
+
+void df_destroy(df_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->status);
+  delete c;
+}
+
+int df_set_precision(df_ctx* c, int slices) {
+  if (!c) return DF_EINVAL;
+  if (slices < 0 || slices > kMaxSlices) return fail(c, DF_EINVAL, "slices must be 0..8");
+  c->slices = slices;
+  return DF_OK;
+}
+
+int df_get_precision(const df_ctx* c) { return c ? c->slices : DF_EINVAL; }
+
+int df_set_pblk(df_ctx* c, int pblk) {
+  if (!c) return DF_EINVAL;
+  if (pblk < 1 || pblk > 1024) return fail(c, DF_EINVAL, "pblk must be 1..1024");
+  c->pblk = pblk;
+  return DF_OK;
+}
+
+int df_set_k_groups(df_ctx* c, int groups) {
+  if (!c) return DF_EINVAL;
+  if (groups < 0 || groups > 4096) return fail(c, DF_EINVAL, "groups must be 0..4096");
+  c->k_groups_req = groups;
+  return DF_OK;
+}
+
+int df_get_k_groups(const df_ctx* c) { return c ? c->k_groups_used : DF_EINVAL; }
+
+int df_workspace_size(df_ctx* c, int64_t naux, int64_t nao, int64_t nocc, int layout,
+                      size_t* bytes) {
+  const int rc = check_shape(c, layout, naux, nao, nocc);
+  if (rc) return rc;
+  if (!bytes) return fail(c, DF_EINVAL, "null bytes");
+  *bytes = make_plan(c, naux, nao, nocc).total;
+  return DF_OK;
+}
+
+int df_set_workspace(df_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c) return DF_EINVAL;
+  if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) & 255))
+    return fail(c, DF_EINVAL, "workspace must be 256-byte aligned");
+  c->ws = reinterpret_cast<char*>(dev_ptr);
+  c->ws_bytes = dev_ptr ? bytes : 0;
+  return DF_OK;
+}
+
+int df_b_exponents(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao,
+                   int32_t* b_exp) {
+  const int rc = check_shape(c, layout, naux, nao, 1);
+  if (rc) return rc;
+  if (!B || !b_exp) return fail(c, DF_EINVAL, "null pointer");
+  DF_HIP(launch_row_exp(c->stream, B, naux * nao, nao, nao, b_exp, c->status), "row_exp");
+  return DF_OK;
+}
+
+int df_slice(df_ctx* c, const double* A, int64_t rows, int64_t cols, int64_t lda, int slices,
+             int8_t* digits, int32_t* row_exp) {
+  if (!c) return DF_EINVAL;
+  if (!A || !digits || !row_exp) return fail(c, DF_EINVAL, "null pointer");
+  if (rows < 0 || cols < 0 || lda < cols) return fail(c, DF_EINVAL, "bad rows/cols/lda");
+  if (slices < 1 || slices > kMaxSlices) return fail(c, DF_EINVAL, "slices must be 1..8");
+  if (rows == 0) return DF_OK;
+  DF_HIP(launch_row_exp(c->stream, A, rows, cols, lda, row_exp, c->status), "row_exp");
+  DF_HIP(launch_slice_rows(c->stream, A, rows, cols, lda, slices, row_exp, digits), "slice_rows");
+  return DF_OK;
+}
+
+int df_build_x(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao,
+               const int32_t* b_exp, const double* C, int64_t nocc, double* X) {
+  Plan p;
+  int rc = common_checks(c, B, layout, naux, nao, C, nocc, p);
+  if (rc) return rc;
+  if (!X) return fail(c, DF_EINVAL, "null X");
+  if (c->slices > 0 && !b_exp) {
+    int32_t* be = at<int32_t>(c, p.off_bexp);
+    DF_HIP(launch_row_exp(c->stream, B, naux * nao, nao, nao, be, c->status), "row_exp");
+    b_exp = be;
+  }
+  return run_x(c, p, B, b_exp, C, X);
+}
+
+int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao,
+                const int32_t* b_exp, const double* C, int64_t nocc, double occ,
+                const double* D, double* J, double* K, double* energies, double* err_bound) {
+  Plan p;
+  int rc = common_checks(c, B, layout, naux, nao, C, nocc, p);
+  if (rc) return rc;
+  if (!D || !J || !K || !energies || !err_bound) return fail(c, DF_EINVAL, "null output or D");
+  if (!(occ == occ) || isinf(occ)) return fail(c, DF_EINVAL, "occ must be finite");
+  const int s = c->slices;
+  hipStream_t st = c->stream;
+  if (!b_exp) {
+    int32_t* be = at<int32_t>(c, p.off_bexp);
+    DF_HIP(launch_row_exp(st, B, naux * nao, nao, nao, be, c->status), "row_exp");
+    b_exp = be;
+  }
+  double* X = at<double>(c, p.off_X);
+  rc = run_x(c, p, B, b_exp, C, X);
+  if (rc) return rc;
+
+  int32_t* F = at<int32_t>(c, p.off_F);
+  double* Kp = at<double>(c, p.off_Kp);
+  unsigned long long* xmax = at<unsigned long long>(c, p.off_xmax);
+  int fstride;
+  if (s == 0) {
+    DF_HIP(launch_k_fp64(st, X, naux, (int)nao, (int)nocc, p.pblk, p.nb, p.groups, Kp), "k_fp64");
+    DF_HIP(launch_xmax_to_exp(st, xmax, (int64_t)p.nb * nao, F), "xmax_to_exp");
+    fstride = (int)nao;
+  } else {
+    int8_t* Xd = at<int8_t>(c, p.off_Xd);
+    DF_HIP(launch_slice_x(st, s, X, naux, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp, xmax, F, Xd),
+           "slice_x");
+    DF_HIP(launch_k_int8(st, s, Xd, F, p.nb, (int)nao, p.nao_pad, p.kbp, p.groups, Kp), "k_int8");
+    fstride = p.nao_pad;
+  }
+  c->k_groups_used = p.groups;
+  DF_HIP(launch_k_reduce(st, Kp, p.groups, (int)nao, occ, K), "k_reduce");
+
+  double* rho = at<double>(c, p.off_rho);
+  DF_HIP(launch_rho(st, B, naux, (int)nao, D, rho), "rho");
+  DF_HIP(launch_j(st, B, naux, (int)nao, rho, p.jsplit, at<double>(c, p.off_Jp), J), "j");
+  DF_HIP(launch_energies(st, rho, naux, D, K, (int)nao, energies), "energies");
+
+  // Error bound.  For s == 0 the FP64 X product is a length-nao dot product
+  // and each exchange partial is one accumulation chain of at most
+  // naux * nocc terms.
+  int32_t* fcol = at<int32_t>(c, p.off_fcol);
+  if (s == 0) DF_HIP(launch_col_exp(st, C, nao, nocc, fcol, c->status), "col_exp");
+  const int64_t kb_full = (int64_t)p.pblk * nocc;
+  const int64_t kb_last = (naux - (int64_t)(p.nb - 1) * p.pblk) * nocc;
+  const double k1 = kappa_of(s, nao);
+  const double k2f = s ? kappa_of(s, kb_full) : kappa_of(0, naux * nocc);
+  const double k2l = s ? kappa_of(s, kb_last) : kappa_of(0, naux * nocc);
+  DF_HIP(launch_bound(st, b_exp, fcol, (int)nocc, F, fstride, naux, (int)nao, p.pblk, p.nb, k1,
+                      k2f, k2l, occ, at<double>(c, p.off_bsc), err_bound),
+         "bound");
+  return DF_OK;
+}
+
+int df_get_status(df_ctx* c) {
+  if (!c) return DF_EINVAL;
+  int h = 0;
+  hipError_t e = hipMemcpyAsync(&h, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "status read");
+  e = launch_fill_i32(c->stream, c->status, 1, 0);
+  if (e != hipSuccess) return hip_fail(c, e, "status clear");
+  return (h & kStatusNonFinite) ? DF_ENONFINITE : DF_OK;
+}
+
+const char* df_last_error(const df_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int df_debug_slice_gemm_i32(df_ctx* c, const int8_t* a_dig, const int8_t* b_dig, int64_t m,
+                            int64_t n, int64_t k, int s, int32_t* partials) {
+  if (!c) return DF_EINVAL;
+  if (!a_dig || !b_dig || !partials) return fail(c, DF_EINVAL, "null pointer");
+  if (m < 1 || n < 1 || k < 1 || s < 1 || s > kMaxSlices) return fail(c, DF_EINVAL, "bad shape");
+  if (k > 131072) return fail(c, DF_EOVERFLOW_GUARD, "k > 131072");
+  const int64_t mp = round_up(m, 64), np = round_up(n, 64), kpd = round_up(k, 64);
+  const size_t need_a = (size_t)s * mp * kpd, need_b = (size_t)s * np * kpd;
+  const size_t need = (need_a + 255) / 256 * 256 + need_b;
+  if (!c->ws || c->ws_bytes < need) return fail(c, DF_EWORKSPACE, "workspace too small");
+  int8_t* wa = at<int8_t>(c, 0);
+  int8_t* wb = at<int8_t>(c, (need_a + 255) / 256 * 256);
+  DF_HIP(launch_debug_pairs(c->stream, s, a_dig, b_dig, m, n, k, wa, wb, partials), "debug_pairs");
+  return DF_OK;
+}
+
+}  // extern "C"

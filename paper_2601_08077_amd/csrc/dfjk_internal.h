@@ -1,0 +1,106 @@
+// Internal declarations shared by the HIP translation units of libdfjk.
+// gfx950 (CDNA4) only: 64-wide wavefronts, INT8 and FP64 MFMA.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+namespace dfjk {
+
+constexpr int kWave = 64;
+constexpr int kMaxSlices = 8;
+constexpr int kStatusNonFinite = 1;
+
+// Exponent e with 2^(e-1) <= m < 2^e for m > 0, and 0 for m == 0.
+__device__ __forceinline__ int exp_of_max(double m) {
+  int e = 0;
+  if (m != 0.0) (void)frexp(m, &e);
+  return e;
+}
+
+// Balanced base-256 digits of N = trunc(a * 2^(62 - e)), |N| < 2^62, packed in
+// one word: byte 7 holds d_1 (most significant, |d_1| <= 64), byte 0 holds d_8.
+// Adding 0x80 to each of the seven low bytes and flipping their top bit turns
+// the two's-complement bytes of N into the balanced digits in [-128, 127]
+// (each low byte u becomes u - 128 once the carries of the +0x80 have moved
+// into the byte above).
+__device__ __forceinline__ uint64_t digit_word(double a, int e) {
+  const long long n = (long long)ldexp(a, 62 - e);
+  const unsigned long long bias = 0x0080808080808080ull;
+  return ((unsigned long long)n + bias) ^ bias;
+}
+
+// Digit k (1-based, 1 = most significant) of a digit word, as a byte.
+__device__ __forceinline__ uint32_t digit_byte(uint64_t w, int k) {
+  return (uint32_t)(w >> (8 * (8 - k))) & 0xffu;
+}
+
+__device__ __forceinline__ double abs_max_bits_to_double(unsigned long long b) {
+  return __longlong_as_double((long long)b);
+}
+
+}  // namespace dfjk
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (each defined next to its kernels); all enqueue on `st`.
+// ---------------------------------------------------------------------------
+namespace dfjk {
+
+// slicing.hip
+hipError_t launch_row_exp(hipStream_t st, const double* A, int64_t rows, int64_t cols,
+                          int64_t lda, int32_t* e, int* status);
+hipError_t launch_col_exp(hipStream_t st, const double* C, int64_t nao, int64_t nocc,
+                          int32_t* f, int* status);
+hipError_t launch_slice_rows(hipStream_t st, const double* A, int64_t rows, int64_t cols,
+                             int64_t lda, int s, const int32_t* e, int8_t* digits);
+// C digits in the operand layout of the INT8 X product: [s][ncp][kp], k in the
+// slot order of the B-tile loader, zero padded.
+hipError_t launch_slice_c(hipStream_t st, const double* C, int64_t nao, int64_t nocc, int s,
+                          const int32_t* f, int ncp, int kp, int8_t* dC);
+hipError_t launch_fill_u64(hipStream_t st, unsigned long long* p, int64_t n,
+                           unsigned long long v);
+hipError_t launch_fill_i32(hipStream_t st, int* p, int64_t n, int v);
+
+// int8_gemm.hip
+hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, int nao,
+                         const int32_t* b_exp, const int8_t* dC, int ncp, int kp,
+                         const int32_t* f_col, int nocc, double* X, unsigned long long* xmax,
+                         int pblk);
+hipError_t launch_slice_x(hipStream_t st, int s, const double* X, int64_t naux, int nao,
+                          int nocc, int pblk, int nao_pad, int kbp,
+                          const unsigned long long* xmax, int32_t* F, int8_t* Xd);
+hipError_t launch_k_int8(hipStream_t st, int s, const int8_t* Xd, const int32_t* F, int nb,
+                         int nao, int nao_pad, int kbp, int groups, double* Kp);
+hipError_t launch_debug_pairs(hipStream_t st, int s, const int8_t* a_dig, const int8_t* b_dig,
+                              int64_t m, int64_t n, int64_t k, int8_t* ws_a, int8_t* ws_b,
+                              int32_t* partials);
+
+// fp64_gemm.hip
+hipError_t launch_x_fp64(hipStream_t st, const double* B, int64_t naux, int nao,
+                         const double* C, int nocc, double* X, unsigned long long* xmax,
+                         int pblk);
+hipError_t launch_k_fp64(hipStream_t st, const double* X, int64_t naux, int nao, int nocc,
+                         int pblk, int nb, int groups, double* Kp);
+hipError_t launch_xmax_to_exp(hipStream_t st, const unsigned long long* xmax, int64_t n,
+                              int32_t* F);
+
+// jk.hip
+hipError_t launch_rho(hipStream_t st, const double* B, int64_t naux, int nao, const double* D,
+                      double* rho);
+hipError_t launch_j(hipStream_t st, const double* B, int64_t naux, int nao, const double* rho,
+                    int jsplit, double* Jp, double* J);
+hipError_t launch_k_reduce(hipStream_t st, const double* Kp, int groups, int nao, double occ,
+                           double* K);
+hipError_t launch_energies(hipStream_t st, const double* rho, int64_t naux, const double* D,
+                           const double* K, int nao, double* energies);
+// Error bound of the blocked K; kappa1 / kappa2 per block supplied by the host.
+hipError_t launch_bound(hipStream_t st, const int32_t* b_exp, const int32_t* f_col, int nocc,
+                        const int32_t* F, int fstride, int64_t naux, int nao, int pblk, int nb,
+                        double kappa1, double kappa2_full, double kappa2_last, double occ,
+                        double* scratch,
+                        double* err_bound);
+
+}  // namespace dfjk

@@ -1,0 +1,204 @@
+// Native FP64 path of the exchange build (the paper's level 0 / standard FP64,
+// Table 1 and Sec. 3.2) on gfx950 v_mfma_f64_16x16x4_f64.
+//
+// MFMA operand layout (checked on gfx950): lane l holds A[l & 15][l >> 4] and
+// B[l >> 4][l & 15]; result register r of lane l is row 4 r + (l >> 4),
+// column (l & 15).
+#include "dfjk_internal.h"
+
+namespace dfjk {
+namespace {
+
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// X = B C (Eq. 5): 64 rows (P, mu) x 16*NF columns per workgroup, k chunks of
+// 16 staged through LDS; 4 waves x 16 rows.  Also the per-(block, mu) max |X|.
+template <int NF>
+__global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, int64_t M, int K,
+                                                const double* __restrict__ C, int nocc,
+                                                double* __restrict__ X,
+                                                unsigned long long* __restrict__ xmax, int nao,
+                                                int pblk) {
+  constexpr int NT = 16 * NF;
+  __shared__ double As[64][17];
+  __shared__ double Cs[16][NT + 1];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int64_t m0 = (int64_t)blockIdx.x * 64;
+  const int n0 = blockIdx.y * NT;
+
+  const int lr = t >> 2, lk = (t & 3) * 4;
+  const int64_t grow = m0 + lr;
+  const bool row_ok = grow < M;
+  const double* brow = B + (row_ok ? grow : 0) * (int64_t)K;
+
+  f64x4 acc[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kk = k0 + lk + j;
+      As[lr][lk + j] = (row_ok && kk < K) ? brow[kk] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      const int idx = t + 256 * j;
+      const int kr = idx / NT, cc = idx - kr * NT;
+      const int kk = k0 + kr, col = n0 + cc;
+      Cs[kr][cc] = (kk < K && col < nocc) ? C[(int64_t)kk * nocc + col] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const double a = As[w * 16 + (l & 15)][kk * 4 + (l >> 4)];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[f] = mfma_f64(a, Cs[kk * 4 + (l >> 4)][f * 16 + (l & 15)], acc[f]);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = m0 + w * 16 + r * 4 + (l >> 4);
+    const bool vr = row < M;
+    double rmax = 0.0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int col = n0 + f * 16 + (l & 15);
+      if (vr && col < nocc) {
+        const double z = acc[f][r];
+        X[row * nocc + col] = z;
+        rmax = fmax(rmax, fabs(z));
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
+    if ((l & 15) == 0 && vr) {
+      const int64_t P = row / nao;
+      const int mu = (int)(row - P * nao);
+      atomicMax(&xmax[(P / pblk) * nao + mu], (unsigned long long)__double_as_longlong(rmax));
+    }
+  }
+}
+
+__device__ __forceinline__ void lower_tile(int idx, int& t1, int& t2) {
+  int r = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+  while (r * (r + 1) / 2 > idx) --r;
+  t1 = r;
+  t2 = idx - r * (r + 1) / 2;
+}
+
+// K partials (Eq. 6): Kp[grp][mu][nu] = sum over P in the aux blocks of group
+// grp and over i of X[P][mu][i] X[P][nu][i], lower 64x64 tiles, 4 waves of
+// 32x32; per P, 16 orbitals at a time are staged through LDS.
+__global__ __launch_bounds__(256) void k_k_fp64(const double* __restrict__ X, int64_t naux,
+                                                int nao, int nocc, int pblk, int nb, int groups,
+                                                double* __restrict__ Kp) {
+  __shared__ double As[64][17];
+  __shared__ double Bs[64][17];
+  int t1, t2;
+  lower_tile(blockIdx.x, t1, t2);
+  const int grp = blockIdx.y;
+  const int64_t b_lo = (int64_t)grp * nb / groups, b_hi = (int64_t)(grp + 1) * nb / groups;
+  const int64_t p_lo = b_lo * pblk;
+  const int64_t p_hi = b_hi * pblk < naux ? b_hi * pblk : naux;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int lr = t >> 2, li = (t & 3) * 4;
+  const int mu_ld = t1 * 64 + lr, nu_ld = t2 * 64 + lr;
+
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  for (int64_t P = p_lo; P < p_hi; ++P) {
+    const double* xp = X + P * nao * (int64_t)nocc;
+    for (int i0 = 0; i0 < nocc; i0 += 16) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = i0 + li + j;
+        As[lr][li + j] = (mu_ld < nao && i < nocc) ? xp[(int64_t)mu_ld * nocc + i] : 0.0;
+        Bs[lr][li + j] = (nu_ld < nao && i < nocc) ? xp[(int64_t)nu_ld * nocc + i] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const double a0 = As[wr + (l & 15)][kk * 4 + (l >> 4)];
+        const double a1 = As[wr + 16 + (l & 15)][kk * 4 + (l >> 4)];
+        const double b0 = Bs[wc + (l & 15)][kk * 4 + (l >> 4)];
+        const double b1 = Bs[wc + 16 + (l & 15)][kk * 4 + (l >> 4)];
+        acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
+        acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+        acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
+        acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+      }
+      __syncthreads();
+    }
+  }
+
+  double* out = Kp + (int64_t)grp * nao * nao;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int nu = t2 * 64 + wc + j * 16 + (l & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int mu = t1 * 64 + wr + i * 16 + r * 4 + (l >> 4);
+        if (mu < nao && nu < nao) out[(int64_t)mu * nao + nu] = acc[i][j][r];
+      }
+    }
+}
+
+__global__ void k_xmax_to_exp(const unsigned long long* __restrict__ xmax, int64_t n,
+                              int32_t* __restrict__ F) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    F[i] = exp_of_max(abs_max_bits_to_double(xmax[i]));
+}
+
+}  // namespace
+
+hipError_t launch_x_fp64(hipStream_t st, const double* B, int64_t naux, int nao,
+                         const double* C, int nocc, double* X, unsigned long long* xmax,
+                         int pblk) {
+  const int64_t M = naux * nao;
+  if (M <= 0 || nocc <= 0) return hipSuccess;
+  const unsigned gx = (unsigned)((M + 63) / 64);
+  if (nocc > 64) {
+    hipLaunchKernelGGL((k_x_fp64<6>), dim3(gx, (nocc + 95) / 96), dim3(256), 0, st, B, M, nao, C,
+                       nocc, X, xmax, nao, pblk);
+  } else if (nocc > 32) {
+    hipLaunchKernelGGL((k_x_fp64<4>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X, xmax,
+                       nao, pblk);
+  } else {
+    hipLaunchKernelGGL((k_x_fp64<2>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X, xmax,
+                       nao, pblk);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_k_fp64(hipStream_t st, const double* X, int64_t naux, int nao, int nocc,
+                         int pblk, int nb, int groups, double* Kp) {
+  const int nt = (nao + 63) / 64;
+  hipLaunchKernelGGL(k_k_fp64, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)groups), dim3(256),
+                     0, st, X, naux, nao, nocc, pblk, nb, groups, Kp);
+  return hipGetLastError();
+}
+
+hipError_t launch_xmax_to_exp(hipStream_t st, const unsigned long long* xmax, int64_t n,
+                              int32_t* F) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_xmax_to_exp, dim3((unsigned)g), dim3(256), 0, st, xmax, n, F);
+  return hipGetLastError();
+}
+
+}  // namespace dfjk

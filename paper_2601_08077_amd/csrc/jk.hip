@@ -1,0 +1,254 @@
+// Coulomb part (Eqs. 3-4), the exchange reduction across aux-block groups,
+// the energies and the error bound.  These passes are HBM-bound streams over
+// B (rho, J) or tiny reductions; all sums run in a fixed order (deterministic).
+#include "dfjk_internal.h"
+
+namespace dfjk {
+namespace {
+
+__device__ __forceinline__ double block_sum_256(double v, double* sh) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (t == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// rho_P = sum_{mu,nu} B[P][mu][nu] D[mu][nu] (Eq. 3): one workgroup per P.
+__global__ __launch_bounds__(256) void k_rho(const double* __restrict__ B, int64_t naux,
+                                             int64_t nn, const double* __restrict__ D,
+                                             double* __restrict__ rho) {
+  __shared__ double sh[4];
+  const int64_t P = blockIdx.x;
+  const double* bp = B + P * nn;
+  double acc0 = 0.0, acc1 = 0.0;
+  const int t = threadIdx.x;
+  if ((nn & 1) == 0) {
+    const double2* b2 = reinterpret_cast<const double2*>(bp);
+    const double2* d2 = reinterpret_cast<const double2*>(D);
+    for (int64_t i = t; i < nn / 2; i += 256) {
+      const double2 b = b2[i], d = d2[i];
+      acc0 = fma(b.x, d.x, acc0);
+      acc1 = fma(b.y, d.y, acc1);
+    }
+  } else {
+    for (int64_t i = t; i < nn; i += 256) acc0 = fma(bp[i], D[i], acc0);
+  }
+  const double r = block_sum_256(acc0 + acc1, sh);
+  if (t == 0) rho[P] = r;
+}
+
+// J partials (Eq. 4): Jp[split][e] = sum over P of the split of rho_P B[P][e],
+// two consecutive elements per thread.
+__global__ __launch_bounds__(256) void k_j(const double* __restrict__ B, int64_t naux, int64_t nn,
+                                           const double* __restrict__ rho, int jsplit,
+                                           double* __restrict__ out) {
+  const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
+  const int split = blockIdx.y;
+  const int64_t p_lo = (int64_t)split * naux / jsplit, p_hi = (int64_t)(split + 1) * naux / jsplit;
+  if (e0 >= nn) return;
+  double a0 = 0.0, a1 = 0.0;
+  if (e0 + 1 < nn && (nn & 1) == 0) {
+    for (int64_t P = p_lo; P < p_hi; ++P) {
+      const double2 b = *reinterpret_cast<const double2*>(B + P * nn + e0);
+      const double r = rho[P];
+      a0 = fma(r, b.x, a0);
+      a1 = fma(r, b.y, a1);
+    }
+    out[split * nn + e0] = a0;
+    out[split * nn + e0 + 1] = a1;
+  } else {
+    for (int64_t P = p_lo; P < p_hi; ++P) {
+      const double r = rho[P];
+      a0 = fma(r, B[P * nn + e0], a0);
+      if (e0 + 1 < nn) a1 = fma(r, B[P * nn + e0 + 1], a1);
+    }
+    out[split * nn + e0] = a0;
+    if (e0 + 1 < nn) out[split * nn + e0 + 1] = a1;
+  }
+}
+
+__global__ void k_sum_splits(const double* __restrict__ Jp, int jsplit, int64_t nn,
+                             double* __restrict__ J) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int s = 0; s < jsplit; ++s) v += Jp[s * nn + e];
+    J[e] = v;
+  }
+}
+
+// K[mu][nu] = K[nu][mu] = occ * sum_grp Kp[grp][mu][nu] (mu >= nu), groups ascending.
+__global__ void k_k_reduce(const double* __restrict__ Kp, int groups, int nao, double occ,
+                           double* __restrict__ K) {
+  const int64_t nn = (int64_t)nao * nao;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int mu = (int)(e / nao), nu = (int)(e - (int64_t)mu * nao);
+    if (mu < nu) continue;
+    double v = 0.0;
+    for (int g = 0; g < groups; ++g) v += Kp[g * nn + e];
+    v *= occ;
+    K[e] = v;
+    K[(int64_t)nu * nao + mu] = v;
+  }
+}
+
+// energies[0] = 1/2 sum_P rho_P^2, energies[1] = -1/4 sum D K (one workgroup).
+__global__ __launch_bounds__(256) void k_energies(const double* __restrict__ rho, int64_t naux,
+                                                  const double* __restrict__ D,
+                                                  const double* __restrict__ K, int64_t nn,
+                                                  double* __restrict__ energies) {
+  __shared__ double sh[4];
+  const int t = threadIdx.x;
+  double a = 0.0;
+  for (int64_t i = t; i < naux; i += 256) a = fma(rho[i], rho[i], a);
+  const double ej = block_sum_256(a, sh);
+  double b = 0.0;
+  for (int64_t i = t; i < nn; i += 256) b = fma(D[i], K[i], b);
+  const double ex = block_sum_256(b, sh);
+  if (t == 0) {
+    energies[0] = 0.5 * ej;
+    energies[1] = -0.25 * ex;
+  }
+}
+
+// Per (block, mu): A = nao kappa1 Fsum sum_{P in b} 2^e_B, dmax = nao kappa1 Fmax
+// max_{P in b} 2^e_B, pf = 2^F.  Fsum / Fmax over the orbital exponents f_i.
+__global__ void k_bound_prep(const int32_t* __restrict__ b_exp, const int32_t* __restrict__ f_col,
+                             int nocc, const int32_t* __restrict__ F, int fstride, int64_t naux,
+                             int nao, int pblk, int nb, double kappa1,
+                             double* __restrict__ scratch) {
+  double fsum = 0.0, fmx = 0.0;
+  for (int i = 0; i < nocc; ++i) {
+    const double v = ldexp(1.0, f_col[i]);
+    fsum += v;
+    fmx = fmax(fmx, v);
+  }
+  const int64_t n = (int64_t)nb * nao;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / nao), mu = (int)(idx - (int64_t)b * nao);
+    const int64_t p0 = (int64_t)b * pblk;
+    const int64_t p1 = p0 + pblk < naux ? p0 + pblk : naux;
+    double se = 0.0, me = 0.0;
+    for (int64_t P = p0; P < p1; ++P) {
+      const double v = ldexp(1.0, b_exp[P * nao + mu]);
+      se += v;
+      me = fmax(me, v);
+    }
+    scratch[3 * idx + 0] = nao * kappa1 * fsum * se;
+    scratch[3 * idx + 1] = nao * kappa1 * fmx * me;
+    scratch[3 * idx + 2] = ldexp(1.0, F[(int64_t)b * fstride + mu]);
+  }
+}
+
+// bound(mu, nu) = |occ| [ sum_b (A_mu pf_nu + (pf_mu + dmax_mu) A_nu + kb pf_mu pf_nu kappa2_b)
+//                 + (nb - 1) u (1 + u)^nb sum_b kb pf_mu pf_nu (1 + kappa2_b) ]
+//                 (+ u |occ| kabs when occ is not a power of two); max over (mu, nu).
+__global__ __launch_bounds__(256) void k_bound(const double* __restrict__ scratch, int nao, int nb,
+                                               int64_t naux, int pblk, int nocc,
+                                               double kappa2_full, double kappa2_last, double occ,
+                                               int occ_pow2, double* __restrict__ err_bound) {
+  const double u = 0x1p-53;
+  const double accf = (nb - 1) * u * pow(1.0 + u, (double)nb);
+  double best = 0.0;
+  const int64_t nn = (int64_t)nao * nao;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int mu = (int)(e / nao), nu = (int)(e - (int64_t)mu * nao);
+    double sum = 0.0, kabs = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const double* sm = scratch + 3 * ((int64_t)b * nao + mu);
+      const double* sn = scratch + 3 * ((int64_t)b * nao + nu);
+      const int64_t p0 = (int64_t)b * pblk;
+      const int64_t kb = ((p0 + pblk < naux ? p0 + pblk : naux) - p0) * nocc;
+      const double pp = sm[2] * sn[2];
+      const double k2 = b == nb - 1 ? kappa2_last : kappa2_full;
+      sum += sm[0] * sn[2] + (sm[2] + sm[1]) * sn[0] + (double)kb * pp * k2;
+      kabs += (double)kb * pp * (1.0 + k2);
+    }
+    double bound = fabs(occ) * (sum + accf * kabs);
+    if (!occ_pow2) bound += u * fabs(occ) * kabs;
+    best = fmax(best, bound);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(err_bound),
+              (unsigned long long)__double_as_longlong(best));
+}
+
+__global__ void k_zero_f64(double* p) { *p = 0.0; }
+
+}  // namespace
+
+hipError_t launch_rho(hipStream_t st, const double* B, int64_t naux, int nao, const double* D,
+                      double* rho) {
+  if (naux <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rho, dim3((unsigned)naux), dim3(256), 0, st, B, naux,
+                     (int64_t)nao * nao, D, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_j(hipStream_t st, const double* B, int64_t naux, int nao, const double* rho,
+                    int jsplit, double* Jp, double* J) {
+  const int64_t nn = (int64_t)nao * nao;
+  const unsigned gx = (unsigned)((nn + 511) / 512);
+  if (jsplit <= 1) {
+    hipLaunchKernelGGL(k_j, dim3(gx, 1), dim3(256), 0, st, B, naux, nn, rho, 1, J);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_j, dim3(gx, (unsigned)jsplit), dim3(256), 0, st, B, naux, nn, rho, jsplit, Jp);
+  int64_t g = (nn + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)g), dim3(256), 0, st, Jp, jsplit, nn, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_k_reduce(hipStream_t st, const double* Kp, int groups, int nao, double occ,
+                           double* K) {
+  const int64_t nn = (int64_t)nao * nao;
+  int64_t g = (nn + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_k_reduce, dim3((unsigned)g), dim3(256), 0, st, Kp, groups, nao, occ, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_energies(hipStream_t st, const double* rho, int64_t naux, const double* D,
+                           const double* K, int nao, double* energies) {
+  hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, st, rho, naux, D, K, (int64_t)nao * nao,
+                     energies);
+  return hipGetLastError();
+}
+
+hipError_t launch_bound(hipStream_t st, const int32_t* b_exp, const int32_t* f_col, int nocc,
+                        const int32_t* F, int fstride, int64_t naux, int nao, int pblk, int nb,
+                        double kappa1, double kappa2_full, double kappa2_last, double occ,
+                        double* scratch,
+                        double* err_bound) {
+  const int64_t n = (int64_t)nb * nao;
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_bound_prep, dim3((unsigned)g), dim3(256), 0, st, b_exp, f_col, nocc, F,
+                     fstride, naux, nao, pblk, nb, kappa1, scratch);
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(1), 0, st, err_bound);
+  int occ_pow2 = 0;
+  {
+    int ex = 0;
+    const double m = frexp(occ, &ex);
+    occ_pow2 = (m == 0.5 || m == -0.5) ? 1 : 0;
+  }
+  const int64_t nn = (int64_t)nao * nao;
+  int64_t g2 = (nn + 255) / 256;
+  if (g2 > 2048) g2 = 2048;
+  hipLaunchKernelGGL(k_bound, dim3((unsigned)g2), dim3(256), 0, st, scratch, nao, nb, naux, pblk,
+                     nocc, kappa2_full, kappa2_last, occ, occ_pow2, err_bound);
+  return hipGetLastError();
+}
+
+}  // namespace dfjk

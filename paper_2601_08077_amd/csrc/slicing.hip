@@ -1,0 +1,146 @@
+// Exponents and INT8 digit planes of FP64 operands (Sec. 3.2: s INT8 splits per
+// input; per-row power-of-two scaling).  gfx950.
+#include "dfjk_internal.h"
+
+namespace dfjk {
+namespace {
+
+// One wavefront per row: e[r] = exponent of max_c |A[r][c]|; NaN/Inf -> status.
+__global__ __launch_bounds__(256) void k_row_exp(const double* __restrict__ A, int64_t rows,
+                                                 int64_t cols, int64_t lda,
+                                                 int32_t* __restrict__ e, int* status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r = wid; r < rows; r += nw) {
+    const double* a = A + r * lda;
+    double m = 0.0;
+    bool bad = false;
+    for (int64_t c = lane; c < cols; c += kWave) {
+      const double v = a[c];
+      bad |= !isfinite(v);
+      m = fmax(m, fabs(v));
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (__any(bad) && lane == 0) atomicOr(status, kStatusNonFinite);
+    if (lane == 0) e[r] = exp_of_max(m);
+  }
+}
+
+// f[i] = exponent of max_nu |C[nu][i]| (the columns of C are the rows of the
+// right operand of Eq. 5 over its contraction index nu).
+__global__ void k_col_exp(const double* __restrict__ C, int64_t nao, int64_t nocc,
+                          int32_t* __restrict__ f, int* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nocc) return;
+  double m = 0.0;
+  bool bad = false;
+  for (int64_t k = 0; k < nao; ++k) {
+    const double v = C[k * nocc + i];
+    bad |= !isfinite(v);
+    m = fmax(m, fabs(v));
+  }
+  if (bad) atomicOr(status, kStatusNonFinite);
+  f[i] = exp_of_max(m);
+}
+
+// digits[a][r][c] for a = 0..s-1 (a = 0 is d_1).
+__global__ void k_slice_rows(const double* __restrict__ A, int64_t rows, int64_t cols,
+                             int64_t lda, int s, const int32_t* __restrict__ e,
+                             int8_t* __restrict__ digits) {
+  const int64_t n = rows * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / cols, c = idx - r * cols;
+    const uint64_t w = digit_word(A[r * lda + c], e[r]);
+    for (int a = 0; a < s; ++a) digits[(int64_t)a * n + idx] = (int8_t)digit_byte(w, a + 1);
+  }
+}
+
+// Digit planes of C^T in the right-operand layout of the INT8 X product:
+// dC[a][i][p] with p = 64 c + 16 q + (2 j + h) holding k = 64 c + 8 j + 2 q + h
+// (the order in which the B-tile loader hands k to its four lane groups).
+__global__ void k_slice_c(const double* __restrict__ C, int64_t nao, int64_t nocc, int s,
+                          const int32_t* __restrict__ f, int ncp, int kp,
+                          int8_t* __restrict__ dC) {
+  const int64_t n = (int64_t)ncp * kp;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / kp);
+    const int p = (int)(idx - (int64_t)i * kp);
+    const int c = p >> 6, q = (p >> 4) & 3, slot = p & 15;
+    const int j = slot >> 1, h = slot & 1;
+    const int64_t k = (int64_t)c * 64 + 8 * j + 2 * q + h;
+    uint64_t w = 0;
+    if (i < nocc && k < nao) w = digit_word(C[k * nocc + i], f[i]);
+    for (int a = 0; a < s; ++a) dC[(int64_t)a * n + idx] = (int8_t)digit_byte(w, a + 1);
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_i32(int* p, int64_t n, int v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_row_exp(hipStream_t st, const double* A, int64_t rows, int64_t cols,
+                          int64_t lda, int32_t* e, int* status) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_exp, dim3(grid_for(rows * 64, 256)), dim3(256), 0, st, A, rows,
+                     cols, lda, e, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_exp(hipStream_t st, const double* C, int64_t nao, int64_t nocc,
+                          int32_t* f, int* status) {
+  if (nocc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col_exp, dim3(grid_for(nocc, 64)), dim3(64), 0, st, C, nao, nocc, f,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_rows(hipStream_t st, const double* A, int64_t rows, int64_t cols,
+                             int64_t lda, int s, const int32_t* e, int8_t* digits) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slice_rows, dim3(grid_for(rows * cols, 256)), dim3(256), 0, st, A,
+                     rows, cols, lda, s, e, digits);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_c(hipStream_t st, const double* C, int64_t nao, int64_t nocc, int s,
+                          const int32_t* f, int ncp, int kp, int8_t* dC) {
+  hipLaunchKernelGGL(k_slice_c, dim3(grid_for((int64_t)ncp * kp, 256)), dim3(256), 0, st, C,
+                     nao, nocc, s, f, ncp, kp, dC);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(hipStream_t st, unsigned long long* p, int64_t n,
+                           unsigned long long v) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(hipStream_t st, int* p, int64_t n, int v) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace dfjk
