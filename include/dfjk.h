@@ -134,6 +134,32 @@ int df_get_status(df_ctx* ctx);
 /* Text of the last synchronous error of this context ("" if none). */
 const char* df_last_error(const df_ctx* ctx);
 
+/* Stages of one df_build_jk call, in launch order, for df_timing_end. */
+enum df_stage {
+  DF_STAGE_BEXP = 0,      /* row exponents of B (only when b_exp is NULL)        */
+  DF_STAGE_PREP = 1,      /* exponents and digit planes of C                     */
+  DF_STAGE_X = 2,         /* X = B C (Eq. 5): INT8-MFMA slices or FP64 MFMA       */
+  DF_STAGE_SLICE_X = 3,   /* per-(block, mu) exponents and digits of X            */
+  DF_STAGE_K = 4,         /* blocked K partials (Eq. 6): INT8 or FP64 MFMA        */
+  DF_STAGE_K_REDUCE = 5,  /* sum of the block-group partials, occ, mirror         */
+  DF_STAGE_RHO = 6,       /* rho (Eq. 3)                                          */
+  DF_STAGE_J = 7,         /* J (Eq. 4)                                            */
+  DF_STAGE_ENERGIES = 8,  /* E_J, E_x                                             */
+  DF_STAGE_BOUND = 9,     /* error bound                                          */
+  DF_NSTAGES = 10
+};
+
+/* Per-stage timing with HIP events on the context stream.  df_timing_begin
+ * creates events for up to `max_calls` df_build_jk calls (it allocates, so
+ * call it outside any timed or captured region); every following build
+ * records one event per stage boundary without synchronising.
+ * df_timing_end synchronises, writes the summed milliseconds per stage into
+ * ms_sum[DF_NSTAGES] and the number of timed calls into *ncalls, and frees
+ * the events.  Each stage's time runs from the end of the previous stage to
+ * its own end on the stream. */
+int df_timing_begin(df_ctx* ctx, int max_calls);
+int df_timing_end(df_ctx* ctx, double* ms_sum, int* ncalls);
+
 /* Test hook: the exact int32 products of every kept slice pair, as formed by
  * the INT8 MFMA tiles of the emulated products.  a_dig [s][m][k] and
  * b_dig [s][k][n] are int8 digit planes; partials[p][m][n] receives

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(_HERE, "libdfjk.so")
 
 DF_OK, DF_EINVAL, DF_EWORKSPACE, DF_EHIP, DF_ENONFINITE, DF_EOVERFLOW_GUARD = 0, -1, -2, -3, -4, -5
 DF_DENSE = 0
+STAGES = ("bexp", "prep", "x", "slice_x", "k", "k_reduce", "rho", "j", "energies", "bound")
 
 _c_void_p = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -36,6 +37,8 @@ SIGNATURES = {
                            ctypes.c_double, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "df_get_status": (_int, [_c_void_p]),
     "df_last_error": (ctypes.c_char_p, [_c_void_p]),
+    "df_timing_begin": (_int, [_c_void_p, _int]),
+    "df_timing_end": (_int, [_c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_int)]),
     "df_debug_slice_gemm_i32": (_int, [_c_void_p, _c_void_p, _c_void_p, _i64, _i64, _i64, _int,
                                        _c_void_p]),
 }
@@ -159,6 +162,16 @@ class Context:
         self._check(self.lib.df_build_jk(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp), _ptr(C),
                                          C.shape[1], float(occ), _ptr(D), _ptr(J), _ptr(K),
                                          _ptr(energies), _ptr(err_bound)), "df_build_jk")
+
+    def df_timing_begin(self, max_calls):
+        self._check(self.lib.df_timing_begin(self.h, int(max_calls)), "df_timing_begin")
+
+    def df_timing_end(self):
+        """Returns (dict stage -> summed ms, number of timed calls)."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = _int()
+        self._check(self.lib.df_timing_end(self.h, ms, ctypes.byref(n)), "df_timing_end")
+        return dict(zip(STAGES, list(ms))), n.value
 
     def df_get_status(self):
         return self.lib.df_get_status(self.h)

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "../../include/dfjk.h"
 #include "dfjk_internal.h"
@@ -20,6 +21,10 @@ struct df_ctx {
   size_t ws_bytes = 0;
   int* status = nullptr;  // device word owned by the context
   std::string err;
+  // stage timing: (DF_NSTAGES + 1) events per timed call
+  std::vector<hipEvent_t> ev;
+  int ev_cap = 0;
+  int ev_used = 0;
 };
 
 namespace {
@@ -136,6 +141,13 @@ T* at(df_ctx* c, size_t off) {
   return reinterpret_cast<T*>(c->ws + off);
 }
 
+// Records the boundary event `idx` (0 = call start, i + 1 = end of stage i)
+// of the current timed call, if timing is on and slots remain.
+void mark(df_ctx* c, int idx) {
+  if (c->ev_used >= c->ev_cap) return;
+  (void)hipEventRecord(c->ev[(size_t)c->ev_used * (DF_NSTAGES + 1) + idx], c->stream);
+}
+
 #define DF_HIP(call, where)                       \
   do {                                            \
     hipError_t e_ = (call);                       \
@@ -203,6 +215,7 @@ int df_create(df_ctx** ctx, void* hip_stream) {
 void df_destroy(df_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   (void)hipFree(c->status);
   delete c;
 }
@@ -295,43 +308,64 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
   if (!(occ == occ) || isinf(occ)) return fail(c, DF_EINVAL, "occ must be finite");
   const int s = c->slices;
   hipStream_t st = c->stream;
+  mark(c, 0);
   if (!b_exp) {
     int32_t* be = at<int32_t>(c, p.off_bexp);
     DF_HIP(launch_row_exp(st, B, naux * nao, nao, nao, be, c->status), "row_exp");
     b_exp = be;
   }
+  mark(c, 1 + DF_STAGE_BEXP);
   double* X = at<double>(c, p.off_X);
-  rc = run_x(c, p, B, b_exp, C, X);
-  if (rc) return rc;
+  int32_t* fcol = at<int32_t>(c, p.off_fcol);
+  unsigned long long* xmax = at<unsigned long long>(c, p.off_xmax);
+  DF_HIP(launch_fill_u64(st, xmax, (int64_t)p.nb * p.nao, 0ull), "fill xmax");
+  DF_HIP(launch_col_exp(st, C, nao, nocc, fcol, c->status), "col_exp");
+  int8_t* dC = at<int8_t>(c, p.off_dC);
+  if (s > 0) DF_HIP(launch_slice_c(st, C, nao, nocc, s, fcol, p.ncp, p.kp, dC), "slice_c");
+  mark(c, 1 + DF_STAGE_PREP);
+  if (s == 0) {
+    DF_HIP(launch_x_fp64(st, B, naux, (int)nao, C, (int)nocc, X, xmax, p.pblk), "x_fp64");
+  } else {
+    DF_HIP(launch_x_int8(st, s, B, naux, (int)nao, b_exp, dC, p.ncp, p.kp, fcol, (int)nocc, X,
+                         xmax, p.pblk),
+           "x_int8");
+  }
+  mark(c, 1 + DF_STAGE_X);
 
   int32_t* F = at<int32_t>(c, p.off_F);
   double* Kp = at<double>(c, p.off_Kp);
-  unsigned long long* xmax = at<unsigned long long>(c, p.off_xmax);
+  int8_t* Xd = at<int8_t>(c, p.off_Xd);
   int fstride;
   if (s == 0) {
-    DF_HIP(launch_k_fp64(st, X, naux, (int)nao, (int)nocc, p.pblk, p.nb, p.groups, Kp), "k_fp64");
     DF_HIP(launch_xmax_to_exp(st, xmax, (int64_t)p.nb * nao, F), "xmax_to_exp");
     fstride = (int)nao;
   } else {
-    int8_t* Xd = at<int8_t>(c, p.off_Xd);
     DF_HIP(launch_slice_x(st, s, X, naux, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp, xmax, F, Xd),
            "slice_x");
-    DF_HIP(launch_k_int8(st, s, Xd, F, p.nb, (int)nao, p.nao_pad, p.kbp, p.groups, Kp), "k_int8");
     fstride = p.nao_pad;
   }
+  mark(c, 1 + DF_STAGE_SLICE_X);
+  if (s == 0) {
+    DF_HIP(launch_k_fp64(st, X, naux, (int)nao, (int)nocc, p.pblk, p.nb, p.groups, Kp), "k_fp64");
+  } else {
+    DF_HIP(launch_k_int8(st, s, Xd, F, p.nb, (int)nao, p.nao_pad, p.kbp, p.groups, Kp), "k_int8");
+  }
+  mark(c, 1 + DF_STAGE_K);
   c->k_groups_used = p.groups;
   DF_HIP(launch_k_reduce(st, Kp, p.groups, (int)nao, occ, K), "k_reduce");
+  mark(c, 1 + DF_STAGE_K_REDUCE);
 
   double* rho = at<double>(c, p.off_rho);
   DF_HIP(launch_rho(st, B, naux, (int)nao, D, rho), "rho");
+  mark(c, 1 + DF_STAGE_RHO);
   DF_HIP(launch_j(st, B, naux, (int)nao, rho, p.jsplit, at<double>(c, p.off_Jp), J), "j");
+  mark(c, 1 + DF_STAGE_J);
   DF_HIP(launch_energies(st, rho, naux, D, K, (int)nao, energies), "energies");
+  mark(c, 1 + DF_STAGE_ENERGIES);
 
   // Error bound.  For s == 0 the FP64 X product is a length-nao dot product
   // and each exchange partial is one accumulation chain of at most
   // naux * nocc terms.
-  int32_t* fcol = at<int32_t>(c, p.off_fcol);
-  if (s == 0) DF_HIP(launch_col_exp(st, C, nao, nocc, fcol, c->status), "col_exp");
   const int64_t kb_full = (int64_t)p.pblk * nocc;
   const int64_t kb_last = (naux - (int64_t)(p.nb - 1) * p.pblk) * nocc;
   const double k1 = kappa_of(s, nao);
@@ -340,6 +374,47 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
   DF_HIP(launch_bound(st, b_exp, fcol, (int)nocc, F, fstride, naux, (int)nao, p.pblk, p.nb, k1,
                       k2f, k2l, occ, at<double>(c, p.off_bsc), err_bound),
          "bound");
+  mark(c, 1 + DF_STAGE_BOUND);
+  if (c->ev_used < c->ev_cap) ++c->ev_used;
+  return DF_OK;
+}
+
+int df_timing_begin(df_ctx* c, int max_calls) {
+  if (!c) return DF_EINVAL;
+  if (max_calls < 1 || max_calls > 100000) return fail(c, DF_EINVAL, "max_calls must be 1..100000");
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.assign((size_t)max_calls * (DF_NSTAGES + 1), nullptr);
+  for (auto& e : c->ev) {
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      c->ev_cap = 0;
+      return hip_fail(c, r, "hipEventCreate");
+    }
+  }
+  c->ev_cap = max_calls;
+  c->ev_used = 0;
+  return DF_OK;
+}
+
+int df_timing_end(df_ctx* c, double* ms_sum, int* ncalls) {
+  if (!c) return DF_EINVAL;
+  if (!ms_sum || !ncalls) return fail(c, DF_EINVAL, "null output");
+  for (int i = 0; i < DF_NSTAGES; ++i) ms_sum[i] = 0.0;
+  *ncalls = c->ev_used;
+  hipError_t r = hipStreamSynchronize(c->stream);
+  if (r != hipSuccess) return hip_fail(c, r, "timing sync");
+  for (int call = 0; call < c->ev_used; ++call) {
+    hipEvent_t* e = &c->ev[(size_t)call * (DF_NSTAGES + 1)];
+    for (int i = 0; i < DF_NSTAGES; ++i) {
+      float ms = 0.f;
+      r = hipEventElapsedTime(&ms, e[i], e[i + 1]);
+      if (r != hipSuccess) return hip_fail(c, r, "hipEventElapsedTime");
+      ms_sum[i] += ms;
+    }
+  }
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  c->ev_cap = c->ev_used = 0;
   return DF_OK;
 }
 
