@@ -101,3 +101,46 @@ def random_problem(rng, nao, naux, nocc, L=None, occ=2.0):
     B = 0.5 * (B + B.transpose(0, 2, 1))
     C, D = make_orbitals(rng, nao, nocc, occ)
     return dict(B=np.ascontiguousarray(B), C=C, D=D, r=None, occ=occ)
+
+
+def synthetic_metric(naux, seed=0):
+    """A ~ N(0, 1) (naux x naux) and the SPD metric W = A A^T / naux + I."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((naux, naux))
+    return A @ A.T / naux + np.eye(naux)
+
+
+CONFIG2 = dict(nao=1024, naux=4096, nocc=128, L=12.0, n_iter=20)
+
+
+def perturbed_orbitals(C0, n_iter, seed=0, eps_hi=1e-2, eps_lo=1e-8):
+    """Synthetic SCF sequence of orbitals: C_k = C_0 + eps_k G_k, G_k ~ N(0, 1)
+    drawn k-th from the stream of ``seed``, eps_k falling geometrically from
+    eps_hi to eps_lo over the n_iter iterations."""
+    rng = np.random.default_rng(seed + 1)
+    out = []
+    for k in range(n_iter):
+        t = k / (n_iter - 1) if n_iter > 1 else 0.0
+        eps = eps_hi * (eps_lo / eps_hi) ** t
+        out.append(np.ascontiguousarray(C0 + eps * rng.standard_normal(C0.shape)))
+    return out
+
+
+def raw_three_index_device(nao, naux, L=12.0, seed=0, device="cuda", chunk=128):
+    """T[P, mu, nu] drawn like B above (before whitening), on the GPU, as a
+    (naux, nao * nao) float64 tensor: the stand-in for the integrals (ij|P)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    dmn, dp = _decay(nao, naux, L)
+    dmn_t = torch.from_numpy(dmn).to(device)
+    T = torch.empty((naux, nao, nao), dtype=torch.float64, device=device)
+    for p0 in range(0, naux, chunk):
+        p1 = min(p0 + chunk, naux)
+        G = torch.randn((p1 - p0, nao, nao), generator=gen, dtype=torch.float64, device=device)
+        G.mul_(dmn_t)
+        G = 0.5 * (G + G.transpose(1, 2))
+        G.mul_(torch.from_numpy(dp[p0:p1]).to(device)[:, None, None])
+        T[p0:p1].copy_(G)
+        del G
+    return T.reshape(naux, nao * nao)

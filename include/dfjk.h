@@ -54,7 +54,8 @@ enum df_status {
   DF_EWORKSPACE = -2,      /* workspace missing or smaller than df_workspace_size */
   DF_EHIP = -3,            /* a HIP runtime call failed                          */
   DF_ENONFINITE = -4,      /* NaN/Inf met while slicing (device status)          */
-  DF_EOVERFLOW_GUARD = -5  /* s * pblk * nocc * 2^14 >= 2^31: int32 sums unsafe  */
+  DF_EOVERFLOW_GUARD = -5, /* s * pblk * nocc * 2^14 >= 2^31: int32 sums unsafe  */
+  DF_ENOTSPD = -6          /* non-positive pivot in the metric Cholesky (device)  */
 };
 
 enum df_layout {
@@ -127,7 +128,40 @@ int df_build_jk(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t 
                 const int32_t* b_exp, const double* C, int64_t nocc, double occ,
                 const double* D, double* J, double* K, double* energies, double* err_bound);
 
-/* Device status word (0 or DF_ENONFINITE) accumulated since the last call;
+/* Metric Cholesky (Sec. 2.1, Eq. 2): W [n][n] symmetric positive definite is
+ * overwritten in place by L (lower triangle; the upper triangle is set to 0)
+ * with L L^T = W, in FP64.  A non-positive pivot sets the DF_ENOTSPD device
+ * status (read with df_get_status).  Needs no workspace. */
+int df_metric_cholesky(df_ctx* ctx, double* W, int64_t n);
+
+/* Whitening of the three-index tensor (Sec. 2.1, Eq. 2): B = L^-1 T, with
+ * L [naux][naux] lower triangular from df_metric_cholesky, T [naux][ncols]
+ * (ncols = nao*nao for a dense tensor) and B [naux][ncols] (B must not alias
+ * T).  The aux index of T is contracted with the column index of L^-1.  FP64.
+ * Needs a workspace of at least naux*naux*8 bytes (it holds L^-1). */
+int df_whiten(df_ctx* ctx, const double* L, int64_t naux, const double* T, int64_t ncols,
+              double* B);
+
+/* Density of closed-shell orbitals: D = occ * C C^T (D [nao][nao], C [nao][nocc])
+ * in FP64 on the context stream.  Needs no workspace. */
+int df_density(df_ctx* ctx, const double* C, int64_t nao, int64_t nocc, double occ, double* D);
+
+/* Adaptive precision rule of Sec. 3.2 (Eq. 11, Table 1); host-only, no GPU work.
+ *   df_rule_level(de_rel): Table 1 level for a relative energy change
+ *     (>= 2e-6 -> 4, [5e-9, 2e-6) -> 3, [2e-11, 5e-9) -> 2, [7e-14, 2e-11) -> 1,
+ *     below -> 0; NaN -> 4, i.e. no information).
+ *   df_rule_next_level(level, e_prev, e_now): the level for the next iteration
+ *     after observing E_now; dE_rel = |(E_now - E_prev) / E_now| (|dE| when
+ *     E_now == 0); never returns a lower precision (a higher level) than `level`.
+ *   df_rule_slices(level, fp64_below_level): INT8 split count of a level,
+ *     s = ceil((m + 1) / 8) with m = 23, 31, 39, 47 for levels 4..1; 0 (native
+ *     FP64) for level 0 and for every level <= fp64_below_level (the measured
+ *     point where emulation stops being faster than FP64 on this GPU). */
+int df_rule_level(double de_rel);
+int df_rule_next_level(int level, double e_prev, double e_now);
+int df_rule_slices(int level, int fp64_below_level);
+
+/* Device status word (0, DF_ENONFINITE or DF_ENOTSPD) accumulated since the last call;
  * synchronises the context stream and clears the word. */
 int df_get_status(df_ctx* ctx);
 
@@ -138,11 +172,12 @@ const char* df_last_error(const df_ctx* ctx);
 enum df_stage {
   DF_STAGE_BEXP = 0,      /* row exponents of B (only when b_exp is NULL)        */
   DF_STAGE_PREP = 1,      /* exponents and digit planes of C                     */
-  DF_STAGE_X = 2,         /* X = B C (Eq. 5): INT8-MFMA slices or FP64 MFMA       */
+  DF_STAGE_X = 2,         /* X = B C (Eq. 5), INT8 slices or FP64 MFMA, with the
+                             B.D row dots of rho in the same pass over B         */
   DF_STAGE_SLICE_X = 3,   /* per-(block, mu) exponents and digits of X            */
   DF_STAGE_K = 4,         /* blocked K partials (Eq. 6): INT8 or FP64 MFMA        */
   DF_STAGE_K_REDUCE = 5,  /* sum of the block-group partials, occ, mirror         */
-  DF_STAGE_RHO = 6,       /* rho (Eq. 3)                                          */
+  DF_STAGE_RHO = 6,       /* rho (Eq. 3) from the row dots                        */
   DF_STAGE_J = 7,         /* J (Eq. 4)                                            */
   DF_STAGE_ENERGIES = 8,  /* E_J, E_x                                             */
   DF_STAGE_BOUND = 9,     /* error bound                                          */

@@ -10,7 +10,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdfjk.so")
 
-DF_OK, DF_EINVAL, DF_EWORKSPACE, DF_EHIP, DF_ENONFINITE, DF_EOVERFLOW_GUARD = 0, -1, -2, -3, -4, -5
+DF_OK, DF_EINVAL, DF_EWORKSPACE, DF_EHIP, DF_ENONFINITE, DF_EOVERFLOW_GUARD, DF_ENOTSPD = (
+    0, -1, -2, -3, -4, -5, -6)
 DF_DENSE = 0
 STAGES = ("bexp", "prep", "x", "slice_x", "k", "k_reduce", "rho", "j", "energies", "bound")
 
@@ -37,6 +38,12 @@ SIGNATURES = {
                            ctypes.c_double, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "df_get_status": (_int, [_c_void_p]),
     "df_last_error": (ctypes.c_char_p, [_c_void_p]),
+    "df_metric_cholesky": (_int, [_c_void_p, _c_void_p, _i64]),
+    "df_whiten": (_int, [_c_void_p, _c_void_p, _i64, _c_void_p, _i64, _c_void_p]),
+    "df_density": (_int, [_c_void_p, _c_void_p, _i64, _i64, ctypes.c_double, _c_void_p]),
+    "df_rule_level": (_int, [ctypes.c_double]),
+    "df_rule_next_level": (_int, [_int, ctypes.c_double, ctypes.c_double]),
+    "df_rule_slices": (_int, [_int, _int]),
     "df_timing_begin": (_int, [_c_void_p, _int]),
     "df_timing_end": (_int, [_c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_int)]),
     "df_debug_slice_gemm_i32": (_int, [_c_void_p, _c_void_p, _c_void_p, _i64, _i64, _i64, _int,
@@ -163,6 +170,20 @@ class Context:
                                          C.shape[1], float(occ), _ptr(D), _ptr(J), _ptr(K),
                                          _ptr(energies), _ptr(err_bound)), "df_build_jk")
 
+    def df_metric_cholesky(self, W):
+        """In place: the lower triangle of W becomes L (L L^T = W), upper set to 0."""
+        self._check(self.lib.df_metric_cholesky(self.h, _ptr(W), W.shape[0]), "df_metric_cholesky")
+
+    def df_whiten(self, L, T, B):
+        """B = L^-1 T (T, B: [naux][ncols]); the workspace must hold naux^2 doubles."""
+        naux = L.shape[0]
+        ncols = T.numel() // naux
+        self._check(self.lib.df_whiten(self.h, _ptr(L), naux, _ptr(T), ncols, _ptr(B)), "df_whiten")
+
+    def df_density(self, C, occ, D):
+        self._check(self.lib.df_density(self.h, _ptr(C), C.shape[0], C.shape[1], float(occ), _ptr(D)),
+                    "df_density")
+
     def df_timing_begin(self, max_calls):
         self._check(self.lib.df_timing_begin(self.h, int(max_calls)), "df_timing_begin")
 
@@ -182,3 +203,16 @@ class Context:
         self._check(self.lib.df_debug_slice_gemm_i32(self.h, _ptr(a_dig), _ptr(b_dig), m, n, k,
                                                      int(s), _ptr(partials)),
                     "df_debug_slice_gemm_i32")
+
+
+# -- adaptive precision rule (host-only C functions; no context needed) -----------
+def df_rule_level(de_rel):
+    return load().df_rule_level(float(de_rel))
+
+
+def df_rule_next_level(level, e_prev, e_now):
+    return load().df_rule_next_level(int(level), float(e_prev), float(e_now))
+
+
+def df_rule_slices(level, fp64_below_level=0):
+    return load().df_rule_slices(int(level), int(fp64_below_level))

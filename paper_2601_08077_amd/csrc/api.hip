@@ -70,8 +70,8 @@ double kappa_of(int s, int64_t k) {
 struct Plan {
   int64_t naux, nao, nocc;
   int pblk, nb, nao_pad, kbp, ncp, kp, groups, jsplit;
-  size_t off_bexp, off_fcol, off_dC, off_X, off_xmax, off_F, off_Xd, off_rho, off_Jp, off_Kp,
-      off_bsc, total;
+  size_t off_bexp, off_fcol, off_dC, off_X, off_xmax, off_F, off_Xd, off_rho, off_rowdot,
+      off_Jp, off_Kp, off_bsc, off_esc, total;
 };
 
 size_t carve(size_t& cur, size_t bytes) {
@@ -104,14 +104,16 @@ Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
   p.off_bexp = carve(cur, (size_t)naux * nao * 4);
   p.off_fcol = carve(cur, (size_t)std::max<int64_t>(nocc, 1) * 4);
   p.off_dC = carve(cur, (size_t)kMaxSlices * p.ncp * p.kp);
-  p.off_X = carve(cur, (size_t)naux * nao * nocc * 8);
+  p.off_X = carve(cur, (size_t)p.nb * p.pblk * nao * nocc * 8);  // blocked layout
   p.off_xmax = carve(cur, (size_t)p.nb * nao * 8);
   p.off_F = carve(cur, (size_t)p.nb * p.nao_pad * 4);
   p.off_Xd = carve(cur, (size_t)kMaxSlices * p.nb * p.nao_pad * p.kbp);
   p.off_rho = carve(cur, (size_t)naux * 8);
+  p.off_rowdot = carve(cur, (size_t)naux * nao * 8);
   p.off_Jp = carve(cur, (size_t)(p.jsplit > 1 ? p.jsplit : 0) * nn * 8);
   p.off_Kp = carve(cur, (size_t)p.groups * nn * 8);
   p.off_bsc = carve(cur, (size_t)p.nb * nao * 3 * 8);
+  p.off_esc = carve(cur, (size_t)512 * 8);
   p.total = cur;
   return p;
 }
@@ -161,7 +163,8 @@ int run_x(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp, const
   unsigned long long* xmax = at<unsigned long long>(c, p.off_xmax);
   DF_HIP(launch_fill_u64(c->stream, xmax, (int64_t)p.nb * p.nao, 0ull), "fill xmax");
   if (s == 0) {
-    DF_HIP(launch_x_fp64(c->stream, B, p.naux, (int)p.nao, C, (int)p.nocc, X, xmax, p.pblk),
+    DF_HIP(launch_x_fp64(c->stream, B, p.naux, (int)p.nao, C, (int)p.nocc, X, 0, xmax, p.pblk,
+                         nullptr, nullptr),
            "x_fp64");
     return DF_OK;
   }
@@ -170,7 +173,7 @@ int run_x(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp, const
   DF_HIP(launch_col_exp(c->stream, C, p.nao, p.nocc, fcol, c->status), "col_exp");
   DF_HIP(launch_slice_c(c->stream, C, p.nao, p.nocc, s, fcol, p.ncp, p.kp, dC), "slice_c");
   DF_HIP(launch_x_int8(c->stream, s, B, p.naux, (int)p.nao, b_exp, dC, p.ncp, p.kp, fcol,
-                       (int)p.nocc, X, xmax, p.pblk),
+                       (int)p.nocc, X, 0, xmax, p.pblk, nullptr, nullptr),
          "x_int8");
   return DF_OK;
 }
@@ -323,11 +326,14 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
   int8_t* dC = at<int8_t>(c, p.off_dC);
   if (s > 0) DF_HIP(launch_slice_c(st, C, nao, nocc, s, fcol, p.ncp, p.kp, dC), "slice_c");
   mark(c, 1 + DF_STAGE_PREP);
+  // X in the blocked layout, with the B.D row dots of rho fused into the same pass over B
+  double* rowdot = at<double>(c, p.off_rowdot);
   if (s == 0) {
-    DF_HIP(launch_x_fp64(st, B, naux, (int)nao, C, (int)nocc, X, xmax, p.pblk), "x_fp64");
+    DF_HIP(launch_x_fp64(st, B, naux, (int)nao, C, (int)nocc, X, 1, xmax, p.pblk, D, rowdot),
+           "x_fp64");
   } else {
-    DF_HIP(launch_x_int8(st, s, B, naux, (int)nao, b_exp, dC, p.ncp, p.kp, fcol, (int)nocc, X,
-                         xmax, p.pblk),
+    DF_HIP(launch_x_int8(st, s, B, naux, (int)nao, b_exp, dC, p.ncp, p.kp, fcol, (int)nocc, X, 1,
+                         xmax, p.pblk, D, rowdot),
            "x_int8");
   }
   mark(c, 1 + DF_STAGE_X);
@@ -356,11 +362,12 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
   mark(c, 1 + DF_STAGE_K_REDUCE);
 
   double* rho = at<double>(c, p.off_rho);
-  DF_HIP(launch_rho(st, B, naux, (int)nao, D, rho), "rho");
+  DF_HIP(launch_rho_reduce(st, rowdot, naux, (int)nao, rho), "rho_reduce");
   mark(c, 1 + DF_STAGE_RHO);
   DF_HIP(launch_j(st, B, naux, (int)nao, rho, p.jsplit, at<double>(c, p.off_Jp), J), "j");
   mark(c, 1 + DF_STAGE_J);
-  DF_HIP(launch_energies(st, rho, naux, D, K, (int)nao, energies), "energies");
+  DF_HIP(launch_energies(st, rho, naux, D, K, (int)nao, at<double>(c, p.off_esc), energies),
+         "energies");
   mark(c, 1 + DF_STAGE_ENERGIES);
 
   // Error bound.  For s == 0 the FP64 X product is a length-nao dot product
@@ -418,6 +425,55 @@ int df_timing_end(df_ctx* c, double* ms_sum, int* ncalls) {
   return DF_OK;
 }
 
+int df_metric_cholesky(df_ctx* c, double* W, int64_t n) {
+  if (!c) return DF_EINVAL;
+  if (!W || n < 1 || n > 65536) return fail(c, DF_EINVAL, "bad W or n");
+  DF_HIP(launch_cholesky(c->stream, W, n, c->status), "cholesky");
+  return DF_OK;
+}
+
+int df_whiten(df_ctx* c, const double* L, int64_t naux, const double* T, int64_t ncols, double* B) {
+  if (!c) return DF_EINVAL;
+  if (!L || !T || !B || naux < 1 || naux > 65536 || ncols < 1) return fail(c, DF_EINVAL, "bad arguments");
+  if (B == T) return fail(c, DF_EINVAL, "B must not alias T");
+  const size_t need = (size_t)naux * naux * 8;
+  if (!c->ws || c->ws_bytes < need) return fail(c, DF_EWORKSPACE, "workspace too small for L^-1");
+  double* Linv = at<double>(c, 0);
+  DF_HIP(launch_tri_inverse(c->stream, L, naux, Linv), "tri_inverse");
+  DF_HIP(launch_whiten(c->stream, Linv, naux, T, ncols, B), "whiten");
+  return DF_OK;
+}
+
+int df_density(df_ctx* c, const double* C, int64_t nao, int64_t nocc, double occ, double* D) {
+  if (!c) return DF_EINVAL;
+  if (!C || !D || nao < 1 || nocc < 1 || nocc > nao) return fail(c, DF_EINVAL, "bad arguments");
+  DF_HIP(launch_density(c->stream, C, nao, nocc, occ, D), "density");
+  return DF_OK;
+}
+
+int df_rule_level(double de_rel) {
+  if (de_rel != de_rel) return 4;
+  if (de_rel >= 2e-6) return 4;
+  if (de_rel >= 5e-9) return 3;
+  if (de_rel >= 2e-11) return 2;
+  if (de_rel >= 7e-14) return 1;
+  return 0;
+}
+
+int df_rule_next_level(int level, double e_prev, double e_now) {
+  const double de = e_now - e_prev;
+  const double rel = e_now == 0.0 ? fabs(de) : fabs(de / e_now);
+  const int l = df_rule_level(rel);
+  return l < level ? l : level;
+}
+
+int df_rule_slices(int level, int fp64_below_level) {
+  if (level <= 0 || level <= fp64_below_level) return 0;
+  static const int mbits[5] = {0, 47, 39, 31, 23};
+  const int m = mbits[level > 4 ? 4 : level];
+  return (m + 1 + 7) / 8;
+}
+
 int df_get_status(df_ctx* c) {
   if (!c) return DF_EINVAL;
   int h = 0;
@@ -426,7 +482,9 @@ int df_get_status(df_ctx* c) {
   if (e != hipSuccess) return hip_fail(c, e, "status read");
   e = launch_fill_i32(c->stream, c->status, 1, 0);
   if (e != hipSuccess) return hip_fail(c, e, "status clear");
-  return (h & kStatusNonFinite) ? DF_ENONFINITE : DF_OK;
+  if (h & kStatusNonFinite) return DF_ENONFINITE;
+  if (h & kStatusNotSpd) return DF_ENOTSPD;
+  return DF_OK;
 }
 
 const char* df_last_error(const df_ctx* c) { return c ? c->err.c_str() : "null context"; }

@@ -13,6 +13,7 @@ namespace dfjk {
 constexpr int kWave = 64;
 constexpr int kMaxSlices = 8;
 constexpr int kStatusNonFinite = 1;
+constexpr int kStatusNotSpd = 2;
 
 // Exponent e with 2^(e-1) <= m < 2^e for m > 0, and 0 for m == 0.
 __device__ __forceinline__ int exp_of_max(double m) {
@@ -23,14 +24,27 @@ __device__ __forceinline__ int exp_of_max(double m) {
 
 // Balanced base-256 digits of N = trunc(a * 2^(62 - e)), |N| < 2^62, packed in
 // one word: byte 7 holds d_1 (most significant, |d_1| <= 64), byte 0 holds d_8.
-// Adding 0x80 to each of the seven low bytes and flipping their top bit turns
-// the two's-complement bytes of N into the balanced digits in [-128, 127]
-// (each low byte u becomes u - 128 once the carries of the +0x80 have moved
-// into the byte above).
+// N is built from the bits of a (exact truncation toward zero: the 53-bit
+// significand shifted by exponent(a) - 1075 + 62 - e, then the sign).  Adding
+// 0x80 to each of the seven low bytes and flipping their top bit turns the
+// two's-complement bytes of N into the balanced digits in [-128, 127] (each low
+// byte u becomes u - 128 once the carries of the +0x80 have moved up).
+// Requires |a| < 2^e (e is the exponent of the row maximum).
 __device__ __forceinline__ uint64_t digit_word(double a, int e) {
-  const long long n = (long long)ldexp(a, 62 - e);
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(a);
+  const int be = (int)((bits >> 52) & 0x7ff);
+  const unsigned long long frac = bits & 0x000fffffffffffffull;
+  const unsigned long long mant = be ? (frac | 0x0010000000000000ull) : frac;
+  const int sh = (be ? be : 1) - 1013 - e;  // shift of the significand into N (<= 9)
+  // branch-free: both shifts, then selects (shift counts taken mod 64)
+  const unsigned long long left = mant << (sh & 63);
+  const unsigned long long right = mant >> ((-sh) & 63);
+  unsigned long long mag = sh >= 0 ? left : right;
+  mag = sh <= -64 ? 0ull : mag;
+  const unsigned long long neg = 0ull - (bits >> 63);  // all ones when a < 0
+  const unsigned long long n = (mag ^ neg) - neg;
   const unsigned long long bias = 0x0080808080808080ull;
-  return ((unsigned long long)n + bias) ^ bias;
+  return (n + bias) ^ bias;
 }
 
 // Digit k (1-based, 1 = most significant) of a digit word, as a byte.
@@ -65,11 +79,14 @@ hipError_t launch_fill_u64(hipStream_t st, unsigned long long* p, int64_t n,
 hipError_t launch_fill_i32(hipStream_t st, int* p, int64_t n, int v);
 
 // int8_gemm.hip
+// X layout 0: [naux*nao][nocc]; 1: blocked, X_b rows mu over (P - P0, i) with
+// block stride pblk * nocc.  D / rowdot optional: rowdot[P*nao + mu] = B row . D row.
 hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, int nao,
                          const int32_t* b_exp, const int8_t* dC, int ncp, int kp,
-                         const int32_t* f_col, int nocc, double* X, unsigned long long* xmax,
-                         int pblk);
-hipError_t launch_slice_x(hipStream_t st, int s, const double* X, int64_t naux, int nao,
+                         const int32_t* f_col, int nocc, double* X, int xlayout,
+                         unsigned long long* xmax, int pblk, const double* D, double* rowdot);
+// X in the blocked layout.
+hipError_t launch_slice_x(hipStream_t st, int s, const double* Xb, int64_t naux, int nao,
                           int nocc, int pblk, int nao_pad, int kbp,
                           const unsigned long long* xmax, int32_t* F, int8_t* Xd);
 hipError_t launch_k_int8(hipStream_t st, int s, const int8_t* Xd, const int32_t* F, int nb,
@@ -80,22 +97,35 @@ hipError_t launch_debug_pairs(hipStream_t st, int s, const int8_t* a_dig, const 
 
 // fp64_gemm.hip
 hipError_t launch_x_fp64(hipStream_t st, const double* B, int64_t naux, int nao,
-                         const double* C, int nocc, double* X, unsigned long long* xmax,
-                         int pblk);
-hipError_t launch_k_fp64(hipStream_t st, const double* X, int64_t naux, int nao, int nocc,
+                         const double* C, int nocc, double* X, int xlayout,
+                         unsigned long long* xmax, int pblk, const double* D, double* rowdot);
+// X in the blocked layout.
+hipError_t launch_k_fp64(hipStream_t st, const double* Xb, int64_t naux, int nao, int nocc,
                          int pblk, int nb, int groups, double* Kp);
 hipError_t launch_xmax_to_exp(hipStream_t st, const unsigned long long* xmax, int64_t n,
                               int32_t* F);
 
+// metric.hip (Sec. 2.1, Eq. 2)
+hipError_t launch_cholesky(hipStream_t st, double* A, int64_t n, int* status);
+hipError_t launch_tri_inverse(hipStream_t st, const double* L, int64_t n, double* Linv);
+hipError_t launch_whiten(hipStream_t st, const double* Linv, int64_t naux, const double* T,
+                         int64_t ncols, double* Bout);
+hipError_t launch_density(hipStream_t st, const double* C, int64_t nao, int64_t nocc, double occ,
+                          double* D);
+
 // jk.hip
 hipError_t launch_rho(hipStream_t st, const double* B, int64_t naux, int nao, const double* D,
                       double* rho);
+// rho_P = sum_mu rowdot[P*nao + mu] (fixed order).
+hipError_t launch_rho_reduce(hipStream_t st, const double* rowdot, int64_t naux, int nao,
+                             double* rho);
 hipError_t launch_j(hipStream_t st, const double* B, int64_t naux, int nao, const double* rho,
                     int jsplit, double* Jp, double* J);
 hipError_t launch_k_reduce(hipStream_t st, const double* Kp, int groups, int nao, double occ,
                            double* K);
+// scratch: 2 * 256 doubles.
 hipError_t launch_energies(hipStream_t st, const double* rho, int64_t naux, const double* D,
-                           const double* K, int nao, double* energies);
+                           const double* K, int nao, double* scratch, double* energies);
 // Error bound of the blocked K; kappa1 / kappa2 per block supplied by the host.
 hipError_t launch_bound(hipStream_t st, const int32_t* b_exp, const int32_t* f_col, int nocc,
                         const int32_t* F, int fstride, int64_t naux, int nao, int pblk, int nb,

@@ -14,73 +14,114 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
 }
 
 // X = B C (Eq. 5): 64 rows (P, mu) x 16*NF columns per workgroup, k chunks of
-// 16 staged through LDS; 4 waves x 16 rows.  Also the per-(block, mu) max |X|.
+// 16 staged through LDS; 4 waves x 16 rows.  Also the per-(block, mu) max |X|
+// and, when D is given, the row dots sum_nu B[P][mu][nu] D[mu][nu] (Eq. 3).
+// X layout 0: X[row][i]; 1: blocked (X_b rows mu over (P - P0, i)).
 template <int NF>
 __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, int64_t M, int K,
                                                 const double* __restrict__ C, int nocc,
-                                                double* __restrict__ X,
+                                                double* __restrict__ X, int xlayout,
                                                 unsigned long long* __restrict__ xmax, int nao,
-                                                int pblk) {
+                                                int pblk, const double* __restrict__ D,
+                                                double* __restrict__ rowdot) {
   constexpr int NT = 16 * NF;
-  __shared__ double As[64][17];
-  __shared__ double Cs[16][NT + 1];
+  __shared__ double As[2][64][17];
+  __shared__ double Cs[2][16][NT + 1];
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const int64_t m0 = (int64_t)blockIdx.x * 64;
+  // Workgroups that run together share the basis-row tile (and the rows of D)
+  // and differ in the aux index P.
+  int64_t m0 = (int64_t)blockIdx.x * 64;
+  if (nao % 64 == 0) {
+    const int64_t naux = M / nao;
+    const int64_t mt = blockIdx.x / naux, P = blockIdx.x - mt * naux;
+    m0 = P * nao + mt * 64;
+  }
   const int n0 = blockIdx.y * NT;
 
   const int lr = t >> 2, lk = (t & 3) * 4;
   const int64_t grow = m0 + lr;
   const bool row_ok = grow < M;
   const double* brow = B + (row_ok ? grow : 0) * (int64_t)K;
+  const double* drow = D ? D + (row_ok ? grow % nao : 0) * (int64_t)K : nullptr;
+  double rd = 0.0;
 
   f64x4 acc[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) acc[f] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  double va[4], vc[NF];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int kk = k0 + lk + j;
-      As[lr][lk + j] = (row_ok && kk < K) ? brow[kk] : 0.0;
+      va[j] = (row_ok && kk < K) ? brow[kk] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
       const int idx = t + 256 * j;
       const int kr = idx / NT, cc = idx - kr * NT;
       const int kk = k0 + kr, col = n0 + cc;
-      Cs[kr][cc] = (kk < K && col < nocc) ? C[(int64_t)kk * nocc + col] : 0.0;
+      vc[j] = (kk < K && col < nocc) ? C[(int64_t)kk * nocc + col] : 0.0;
+    }
+  };
+  load(0);
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += 16, buf ^= 1) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) As[buf][lr][lk + j] = va[j];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      const int idx = t + 256 * j;
+      const int kr = idx / NT, cc = idx - kr * NT;
+      Cs[buf][kr][cc] = vc[j];
+    }
+    if (drow && row_ok) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int kk = k0 + lk + j;
+        if (kk < K) rd = fma(va[j], drow[kk], rd);
+      }
     }
     __syncthreads();
+    if (k0 + 16 < K) load(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const double a = As[w * 16 + (l & 15)][kk * 4 + (l >> 4)];
+      const double a = As[buf][w * 16 + (l & 15)][kk * 4 + (l >> 4)];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) acc[f] = mfma_f64(a, Cs[kk * 4 + (l >> 4)][f * 16 + (l & 15)], acc[f]);
+      for (int f = 0; f < NF; ++f)
+        acc[f] = mfma_f64(a, Cs[buf][kk * 4 + (l >> 4)][f * 16 + (l & 15)], acc[f]);
     }
-    __syncthreads();
+  }
+
+  if (rowdot) {
+    rd += __shfl_xor(rd, 1);
+    rd += __shfl_xor(rd, 2);
+    if ((t & 3) == 0 && row_ok && blockIdx.y == 0) rowdot[grow] = rd;
   }
 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int64_t row = m0 + w * 16 + r * 4 + (l >> 4);
     const bool vr = row < M;
+    const int64_t P = vr ? row / nao : 0;
+    const int mu = (int)(row - P * nao);
+    const int64_t b = P / pblk;
+    double* xrow = xlayout ? X + (((b * nao + mu) * pblk + (P - b * pblk)) * (int64_t)nocc)
+                           : X + row * (int64_t)nocc;
     double rmax = 0.0;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const int col = n0 + f * 16 + (l & 15);
       if (vr && col < nocc) {
         const double z = acc[f][r];
-        X[row * nocc + col] = z;
+        xrow[col] = z;
         rmax = fmax(rmax, fabs(z));
       }
     }
 #pragma unroll
     for (int off = 1; off < 16; off <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
-    if ((l & 15) == 0 && vr) {
-      const int64_t P = row / nao;
-      const int mu = (int)(row - P * nao);
-      atomicMax(&xmax[(P / pblk) * nao + mu], (unsigned long long)__double_as_longlong(rmax));
-    }
+    if ((l & 15) == 0 && vr)
+      atomicMax(&xmax[b * nao + mu], (unsigned long long)__double_as_longlong(rmax));
   }
 }
 
@@ -92,24 +133,24 @@ __device__ __forceinline__ void lower_tile(int idx, int& t1, int& t2) {
   t2 = idx - r * (r + 1) / 2;
 }
 
-// K partials (Eq. 6): Kp[grp][mu][nu] = sum over P in the aux blocks of group
-// grp and over i of X[P][mu][i] X[P][nu][i], lower 64x64 tiles, 4 waves of
-// 32x32; per P, 16 orbitals at a time are staged through LDS.
-__global__ __launch_bounds__(256) void k_k_fp64(const double* __restrict__ X, int64_t naux,
+// K partials (Eq. 6): Kp[grp][mu][nu] = sum over the aux blocks b of group grp
+// of X_b X_b^T, with X_b rows contiguous (blocked layout, block stride
+// pblk * nocc); lower 64x64 tiles, 4 waves of 32x32; 16 k at a time staged
+// through LDS (double buffered, next chunk prefetched into registers).
+__global__ __launch_bounds__(256) void k_k_fp64(const double* __restrict__ Xb, int64_t naux,
                                                 int nao, int nocc, int pblk, int nb, int groups,
                                                 double* __restrict__ Kp) {
-  __shared__ double As[64][17];
-  __shared__ double Bs[64][17];
+  __shared__ double As[2][64][17];
+  __shared__ double Bs[2][64][17];
   int t1, t2;
   lower_tile(blockIdx.x, t1, t2);
   const int grp = blockIdx.y;
-  const int64_t b_lo = (int64_t)grp * nb / groups, b_hi = (int64_t)(grp + 1) * nb / groups;
-  const int64_t p_lo = b_lo * pblk;
-  const int64_t p_hi = b_hi * pblk < naux ? b_hi * pblk : naux;
+  const int b_lo = (int)((int64_t)grp * nb / groups), b_hi = (int)((int64_t)(grp + 1) * nb / groups);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int lr = t >> 2, li = (t & 3) * 4;
   const int mu_ld = t1 * 64 + lr, nu_ld = t2 * 64 + lr;
+  const int64_t kfull = (int64_t)pblk * nocc;
 
   f64x4 acc[2][2];
 #pragma unroll
@@ -117,29 +158,51 @@ __global__ __launch_bounds__(256) void k_k_fp64(const double* __restrict__ X, in
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  for (int64_t P = p_lo; P < p_hi; ++P) {
-    const double* xp = X + P * nao * (int64_t)nocc;
-    for (int i0 = 0; i0 < nocc; i0 += 16) {
+  double va[4], vb[4];
+  auto load = [&](int b, int k0) {
+    const int64_t p0 = (int64_t)b * pblk;
+    const int kb = (int)(((p0 + pblk < naux ? p0 + pblk : naux) - p0) * nocc);
+    const double* xa = Xb + ((int64_t)b * nao + mu_ld) * kfull;
+    const double* xb = Xb + ((int64_t)b * nao + nu_ld) * kfull;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int i = i0 + li + j;
-        As[lr][li + j] = (mu_ld < nao && i < nocc) ? xp[(int64_t)mu_ld * nocc + i] : 0.0;
-        Bs[lr][li + j] = (nu_ld < nao && i < nocc) ? xp[(int64_t)nu_ld * nocc + i] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const double a0 = As[wr + (l & 15)][kk * 4 + (l >> 4)];
-        const double a1 = As[wr + 16 + (l & 15)][kk * 4 + (l >> 4)];
-        const double b0 = Bs[wc + (l & 15)][kk * 4 + (l >> 4)];
-        const double b1 = Bs[wc + 16 + (l & 15)][kk * 4 + (l >> 4)];
-        acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
-        acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
-        acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
-        acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
-      }
-      __syncthreads();
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + li + j;
+      va[j] = (mu_ld < nao && k < kb) ? xa[k] : 0.0;
+      vb[j] = (nu_ld < nao && k < kb) ? xb[k] : 0.0;
     }
+  };
+  // flattened (block, k chunk) steps
+  int b = b_lo, k0 = 0;
+  auto kb_of = [&](int bb) {
+    const int64_t p0 = (int64_t)bb * pblk;
+    return (int)(((p0 + pblk < naux ? p0 + pblk : naux) - p0) * nocc);
+  };
+  if (b < b_hi) load(b, 0);
+  int buf = 0;
+  while (b < b_hi) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      As[buf][lr][li + j] = va[j];
+      Bs[buf][lr][li + j] = vb[j];
+    }
+    __syncthreads();
+    int nb2 = b, nk0 = k0 + 16;
+    if (nk0 >= kb_of(b)) { ++nb2; nk0 = 0; }
+    if (nb2 < b_hi) load(nb2, nk0);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const double a0 = As[buf][wr + (l & 15)][kk * 4 + (l >> 4)];
+      const double a1 = As[buf][wr + 16 + (l & 15)][kk * 4 + (l >> 4)];
+      const double b0 = Bs[buf][wc + (l & 15)][kk * 4 + (l >> 4)];
+      const double b1 = Bs[buf][wc + 16 + (l & 15)][kk * 4 + (l >> 4)];
+      acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
+      acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+      acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
+      acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+    }
+    buf ^= 1;
+    b = nb2;
+    k0 = nk0;
   }
 
   double* out = Kp + (int64_t)grp * nao * nao;
@@ -166,29 +229,29 @@ __global__ void k_xmax_to_exp(const unsigned long long* __restrict__ xmax, int64
 }  // namespace
 
 hipError_t launch_x_fp64(hipStream_t st, const double* B, int64_t naux, int nao,
-                         const double* C, int nocc, double* X, unsigned long long* xmax,
-                         int pblk) {
+                         const double* C, int nocc, double* X, int xlayout,
+                         unsigned long long* xmax, int pblk, const double* D, double* rowdot) {
   const int64_t M = naux * nao;
   if (M <= 0 || nocc <= 0) return hipSuccess;
   const unsigned gx = (unsigned)((M + 63) / 64);
   if (nocc > 64) {
     hipLaunchKernelGGL((k_x_fp64<6>), dim3(gx, (nocc + 95) / 96), dim3(256), 0, st, B, M, nao, C,
-                       nocc, X, xmax, nao, pblk);
+                       nocc, X, xlayout, xmax, nao, pblk, D, rowdot);
   } else if (nocc > 32) {
-    hipLaunchKernelGGL((k_x_fp64<4>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X, xmax,
-                       nao, pblk);
+    hipLaunchKernelGGL((k_x_fp64<4>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X,
+                       xlayout, xmax, nao, pblk, D, rowdot);
   } else {
-    hipLaunchKernelGGL((k_x_fp64<2>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X, xmax,
-                       nao, pblk);
+    hipLaunchKernelGGL((k_x_fp64<2>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X,
+                       xlayout, xmax, nao, pblk, D, rowdot);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_k_fp64(hipStream_t st, const double* X, int64_t naux, int nao, int nocc,
+hipError_t launch_k_fp64(hipStream_t st, const double* Xb, int64_t naux, int nao, int nocc,
                          int pblk, int nb, int groups, double* Kp) {
   const int nt = (nao + 63) / 64;
   hipLaunchKernelGGL(k_k_fp64, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)groups), dim3(256),
-                     0, st, X, naux, nao, nocc, pblk, nb, groups, Kp);
+                     0, st, Xb, naux, nao, nocc, pblk, nb, groups, Kp);
   return hipGetLastError();
 }
 

@@ -26,126 +26,214 @@ __device__ __forceinline__ uint32_t pack4(uint64_t w0, uint64_t w1, uint64_t w2,
 }
 
 // ---------------------------------------------------------------------------
-// X = B C.  Tile: 64 rows of (P, mu) x 16*NF columns i; 4 waves x 16 rows.
-// Loader: thread t owns row t/4 and lane-group q = t%4 of each 64-wide k chunk;
-// it reads 8 double pairs at k = 8 j + 2 q + {0, 1}, so each row segment of
-// 64 B is read by 4 consecutive threads.  Slot 2 j + h of group q holds
-// k = 8 j + 2 q + h; the C digit planes are stored in the same slot order.
+// X = B C.  Workgroup: 8 waves, tile 64 rows (P, mu) x 16*NF columns i.  Waves
+// w and w + 4 own rows 16 (w % 4) .. + 15 and split the columns in halves.
+// Lane l of either wave reads row (l & 15) of B and half of the 16 k "slots"
+// of lane group q = l >> 4 (slot 2 j + h of group q holds k = 8 j + 2 q + h;
+// the C digit planes are stored in the same order), slices its 8 values in
+// registers and writes their digits to the LDS A tile; the C digits of the
+// chunk are staged in LDS as well.  The next chunk of B (and D) is prefetched
+// into registers while the current one is multiplied.  Optionally the row
+// dots sum_nu B[P][mu][nu] D[mu][nu] (rho, Eq. 3) are formed from the same B
+// values.
+// X layout 0: X[row][i]; layout 1 (blocked): X_b rows, element
+// ((b nao + mu) pblk + P - P0) nocc + i.
 // ---------------------------------------------------------------------------
-template <int S, int NF>
-__global__ __launch_bounds__(256) void k_x_int8(
+template <int S, int NF, bool FULLK, int KSUB>
+__global__ __launch_bounds__(512) void k_x_int8(
     const double* __restrict__ B, int64_t M, int K, const int32_t* __restrict__ b_exp,
     const int8_t* __restrict__ dC, int ncp, int kp, const int32_t* __restrict__ f_col, int nocc,
-    double* __restrict__ X, unsigned long long* __restrict__ xmax, int nao, int pblk) {
-  constexpr int ROWS = 64, KC = 64, LDS_ROW = 80;  // 16 B pad: conflict-free b128 reads
-  __shared__ __attribute__((aligned(16))) int8_t As[S][ROWS][LDS_ROW];
+    double* __restrict__ X, int xlayout, unsigned long long* __restrict__ xmax, int nao, int pblk,
+    const double* __restrict__ D, double* __restrict__ rowdot) {
+  constexpr int NT = 16 * NF, NFW = NF / 2;
+  constexpr int KC = 64 * KSUB, ROW = KC + 16;  // LDS rows: KC k bytes + 16 B pad
+  constexpr int CUNITS = S * NT * 4 * KSUB;     // 16-byte units of C digits per chunk
+  constexpr int CPER = (CUNITS + 511) / 512;
+  constexpr int NV = 8 * KSUB;                  // B values sliced per lane per chunk
+  __shared__ __attribute__((aligned(16))) int8_t As[S][64][ROW];
+  __shared__ __attribute__((aligned(16))) int8_t Cs[S][NT][ROW];
+  __shared__ double rdx[4][16];
 
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const int64_t m0 = (int64_t)blockIdx.x * ROWS;
-  const int n0 = blockIdx.y * 16 * NF;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
+  const int wrow = w & 3, half = w >> 2;  // waves w and w + 4 share 16 rows
+  // Workgroups that run together share the basis-row tile mu0..mu0+63 (and so
+  // the same rows of D, which stay in L2) and differ in the aux index P.
+  int64_t m0 = (int64_t)blockIdx.x * 64;
+  if (nao % 64 == 0) {
+    const int64_t naux = M / nao;
+    const int64_t mt = blockIdx.x / naux, P = blockIdx.x - mt * naux;
+    m0 = P * nao + mt * 64;
+  }
+  const int n0 = blockIdx.y * NT;
+  const int64_t arow = m0 + wrow * 16 + r16;
+  const bool aok = arow < M;
+  // In every 64-wide k sub-chunk each lane slices 8 of the 16 k slots of its
+  // lane group q: half h of the slots, k = 8 j + 2 q + {0, 1} for
+  // j = 4 h .. 4 h + 3.  Rows past M read row 0 (in bounds); their digits and
+  // sums are discarded.
+  const double* brow = B + (aok ? arow : 0) * (int64_t)K + 2 * q + 32 * half;
+  const int e_a = aok ? b_exp[arow] : 0;
+  const bool want_rd = D != nullptr;
+  const double* drow = (want_rd ? D : B) + (aok ? (arow % nao) : 0) * (int64_t)K + 2 * q + 32 * half;
+  const int nch = (K + KC - 1) / KC;
+  int8_t* adst = &As[0][wrow * 16 + r16][q * 16 + half * 8];
 
-  const int lr = t >> 2, lq = t & 3;
-  const int64_t grow = m0 + lr;
-  const bool row_ok = grow < M;
-  const double* brow = B + (row_ok ? grow : 0) * (int64_t)K;
-  const int e_ld = row_ok ? b_exp[grow] : 0;
-  const bool even_k = (K & 1) == 0;
+  const int8_t* csrc[CPER];
+  int cdst[CPER];
+#pragma unroll
+  for (int i = 0; i < CPER; ++i) {
+    const int u = t + 512 * i;
+    const int uu = u < CUNITS ? u : 0;
+    const int per_plane = NT * 4 * KSUB;
+    const int a = uu / per_plane, rem = uu - a * per_plane;
+    const int col = rem / (4 * KSUB), part = rem - col * (4 * KSUB);
+    csrc[i] = dC + ((int64_t)a * ncp + n0 + col) * kp + part * 16;
+    cdst[i] = (a * NT + col) * ROW + part * 16;
+  }
 
-  i32x4 acc[S][NF];
+  i32x4 acc[S][NFW];
 #pragma unroll
   for (int g = 0; g < S; ++g)
 #pragma unroll
-    for (int f = 0; f < NF; ++f) acc[g][f] = i32x4{0, 0, 0, 0};
+    for (int f = 0; f < NFW; ++f) acc[g][f] = i32x4{0, 0, 0, 0};
+  double rd = 0.0;
 
-  const int nchunks = (K + KC - 1) / KC;
-  for (int c = 0; c < nchunks; ++c) {
-    const int k0 = c * KC;
-    uint64_t wd[16];
+  double v[NV], dv[NV];
+  i32x4 cpre[CPER];
+#define DFJK_X_LOAD(CC)                                                                    \
+  {                                                                                        \
+    const int kb0 = (CC) * KC;                                                             \
+    if (FULLK) {                                                                           \
+      _Pragma("unroll") for (int j = 0; j < NV / 2; ++j) {                                 \
+        const int off = kb0 + 64 * (j >> 2) + 8 * (j & 3);                                 \
+        const double2 p = *reinterpret_cast<const double2*>(brow + off);                   \
+        v[2 * j] = p.x;                                                                    \
+        v[2 * j + 1] = p.y;                                                                \
+      }                                                                                    \
+      if (want_rd) {                                                                       \
+        _Pragma("unroll") for (int j = 0; j < NV / 2; ++j) {                               \
+          const int off = kb0 + 64 * (j >> 2) + 8 * (j & 3);                               \
+          const double2 p = *reinterpret_cast<const double2*>(drow + off);                 \
+          dv[2 * j] = p.x;                                                                 \
+          dv[2 * j + 1] = p.y;                                                             \
+        }                                                                                  \
+      }                                                                                    \
+    } else {                                                                               \
+      _Pragma("unroll") for (int j = 0; j < NV; ++j) {                                     \
+        const int off = kb0 + 64 * (j >> 3) + 8 * ((j >> 1) & 3) + (j & 1);               \
+        const int kk = off + 2 * q + 32 * half;                                            \
+        v[j] = kk < K ? brow[off] : 0.0;                                                   \
+        dv[j] = (want_rd && kk < K) ? drow[off] : 0.0;                                     \
+      }                                                                                    \
+    }                                                                                      \
+    _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                     \
+      if (t + 512 * i < CUNITS) cpre[i] = *reinterpret_cast<const i32x4*>(csrc[i] + kb0);  \
+    }                                                                                      \
+  }
+
+  DFJK_X_LOAD(0)
+  for (int c = 0; c < nch; ++c) {
+    // slice this lane's values into S digit planes (8 bytes per sub-chunk)
+    uint32_t lo[KSUB][S], hi[KSUB][S];
+    {
+      if (want_rd) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int kk = k0 + 8 * j + 2 * lq;
-      double v0 = 0.0, v1 = 0.0;
-      if (row_ok) {
-        if (even_k && kk + 1 < K) {
-          const double2 p = *reinterpret_cast<const double2*>(brow + kk);
-          v0 = p.x;
-          v1 = p.y;
-        } else {
-          if (kk < K) v0 = brow[kk];
-          if (kk + 1 < K) v1 = brow[kk + 1];
+        for (int j = 0; j < NV; ++j) rd = fma(v[j], dv[j], rd);
+      }
+#pragma unroll
+      for (int sub = 0; sub < KSUB; ++sub) {
+        uint64_t wd[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) wd[j] = digit_word(v[8 * sub + j], e_a);
+#pragma unroll
+        for (int a = 0; a < S; ++a) {
+          lo[sub][a] = pack4(wd[0], wd[1], wd[2], wd[3], a + 1);
+          hi[sub][a] = pack4(wd[4], wd[5], wd[6], wd[7], a + 1);
         }
       }
-      wd[2 * j] = digit_word(v0, e_ld);
-      wd[2 * j + 1] = digit_word(v1, e_ld);
     }
-    __syncthreads();
+    __syncthreads();  // previous chunk's LDS reads are done
 #pragma unroll
-    for (int a = 0; a < S; ++a) {
-      uint4 pk;
-      pk.x = pack4(wd[0], wd[1], wd[2], wd[3], a + 1);
-      pk.y = pack4(wd[4], wd[5], wd[6], wd[7], a + 1);
-      pk.z = pack4(wd[8], wd[9], wd[10], wd[11], a + 1);
-      pk.w = pack4(wd[12], wd[13], wd[14], wd[15], a + 1);
-      *reinterpret_cast<uint4*>(&As[a][lr][lq * 16]) = pk;
-    }
-    __syncthreads();
-
-    i32x4 af[S];
-#pragma unroll
-    for (int a = 0; a < S; ++a)
-      af[a] = *reinterpret_cast<const i32x4*>(&As[a][w * 16 + (l & 15)][(l >> 4) * 16]);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const int8_t* cb = dC + (int64_t)(n0 + f * 16 + (l & 15)) * kp + k0 + (l >> 4) * 16;
-      i32x4 bf[S];
-#pragma unroll
-      for (int b = 0; b < S; ++b)
-        bf[b] = *reinterpret_cast<const i32x4*>(cb + (int64_t)b * ncp * kp);
+    for (int sub = 0; sub < KSUB; ++sub)
 #pragma unroll
       for (int a = 0; a < S; ++a)
+        *reinterpret_cast<uint2*>(adst + a * 64 * ROW + sub * 64) = make_uint2(lo[sub][a], hi[sub][a]);
 #pragma unroll
-        for (int b = 0; b < S - a; ++b)
-          acc[a + b][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a + b][f], 0, 0, 0);
+    for (int i = 0; i < CPER; ++i)
+      if (t + 512 * i < CUNITS) *reinterpret_cast<i32x4*>(&Cs[0][0][0] + cdst[i]) = cpre[i];
+    __syncthreads();  // A and C digits of chunk c are in LDS
+    if (c + 1 < nch) DFJK_X_LOAD(c + 1)
+#pragma unroll
+    for (int sub = 0; sub < KSUB; ++sub) {
+      i32x4 af[S];
+#pragma unroll
+      for (int a = 0; a < S; ++a)
+        af[a] = *reinterpret_cast<const i32x4*>(&As[a][wrow * 16 + r16][sub * 64 + q * 16]);
+#pragma unroll
+      for (int f = 0; f < NFW; ++f) {
+        i32x4 bf[S];
+#pragma unroll
+        for (int b = 0; b < S; ++b)
+          bf[b] = *reinterpret_cast<const i32x4*>(
+              &Cs[b][(half * NFW + f) * 16 + r16][sub * 64 + q * 16]);
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+          for (int b = 0; b < S - a; ++b)
+            acc[a + b][f] =
+                __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a + b][f], 0, 0, 0);
+      }
     }
+  }
+#undef DFJK_X_LOAD
+
+  if (rowdot) {
+    // row dot = (lane groups of half 0) + (lane groups of half 1), fixed order
+    rd += __shfl_xor(rd, 16);
+    rd += __shfl_xor(rd, 32);
+    if (half == 1 && q == 0) rdx[wrow][r16] = rd;
+    __syncthreads();
+    if (half == 0 && q == 0 && aok && blockIdx.y == 0) rowdot[arow] = rd + rdx[wrow][r16];
   }
 
   // Recombination, X store, and the per-(block, mu) running max of |X|.
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int64_t row = m0 + w * 16 + (l >> 4) * 4 + r;
+    const int64_t row = m0 + wrow * 16 + q * 4 + r;
     const bool vr = row < M;
     const int er = vr ? b_exp[row] : 0;
+    const int64_t P = vr ? row / nao : 0;
+    const int mu = (int)(row - P * nao);
+    const int64_t b = P / pblk;
+    double* xrow = xlayout ? X + (((b * nao + mu) * pblk + (P - b * pblk)) * (int64_t)nocc)
+                           : X + row * (int64_t)nocc;
     double rmax = 0.0;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const int col = n0 + f * 16 + (l & 15);
+    for (int f = 0; f < NFW; ++f) {
+      const int col = n0 + (half * NFW + f) * 16 + r16;
       if (vr && col < nocc) {
         const int base = er + f_col[col] + 4;
         double z = 0.0;
 #pragma unroll
         for (int g = S + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][f][r], base - 8 * g);
-        X[row * nocc + col] = z;
+        xrow[col] = z;
         rmax = fmax(rmax, fabs(z));
       }
     }
 #pragma unroll
     for (int off = 1; off < 16; off <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
-    if ((l & 15) == 0 && vr) {
-      const int64_t P = row / nao;
-      const int mu = (int)(row - P * nao);
-      const int64_t b = P / pblk;
+    if (r16 == 0 && vr)
       atomicMax(&xmax[b * nao + mu], (unsigned long long)__double_as_longlong(rmax));
-    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Slicing of X_b (rows mu over k = (P - P0) * nocc + i) into Xd[a][b][mu][k],
-// natural k order, zero padded to nao_pad rows and kbp columns.  One thread
-// per 16 consecutive k of one (b, mu).
+// Slicing of X_b (rows mu over k = (P - P0) * nocc + i, stored contiguously by
+// the X kernel's blocked layout) into Xd[a][b][mu][k], natural k order, zero
+// padded to nao_pad rows and kbp columns.  One thread per 16 consecutive k.
 // ---------------------------------------------------------------------------
 template <int S>
-__global__ __launch_bounds__(256) void k_slice_x(const double* __restrict__ X, int64_t naux,
+__global__ __launch_bounds__(256) void k_slice_x(const double* __restrict__ Xb, int64_t naux,
                                                  int nao, int nocc, int pblk, int nb,
                                                  int nao_pad, int kbp,
                                                  const unsigned long long* __restrict__ xmax,
@@ -154,6 +242,7 @@ __global__ __launch_bounds__(256) void k_slice_x(const double* __restrict__ X, i
   const int nkc = kbp >> 4;
   const int64_t total = (int64_t)nb * nao_pad * nkc;
   const int64_t plane = (int64_t)nb * nao_pad * kbp;
+  const int64_t kfull = (int64_t)pblk * nocc;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int kc = (int)(idx % nkc);
@@ -162,20 +251,26 @@ __global__ __launch_bounds__(256) void k_slice_x(const double* __restrict__ X, i
     const int b = (int)(rest / nao_pad);
     const int64_t p0 = (int64_t)b * pblk;
     const int64_t p1 = p0 + pblk < naux ? p0 + pblk : naux;
-    const int kb = (int)(p1 - p0) * nocc;
+    const int kb = (int)((p1 - p0) * nocc);
     int e = 0;
     if (mu < nao) e = exp_of_max(abs_max_bits_to_double(xmax[(int64_t)b * nao + mu]));
     if (kc == 0) F[(int64_t)b * nao_pad + mu] = e;
+    const double* src = Xb + ((int64_t)b * nao + (mu < nao ? mu : 0)) * kfull + kc * 16;
+    const bool full = mu < nao && kc * 16 + 16 <= kb;
     uint64_t wd[16];
+    if (full) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int k = kc * 16 + j;
-      double v = 0.0;
-      if (mu < nao && k < kb) {
-        const int pp = k / nocc, i = k - pp * nocc;
-        v = X[((p0 + pp) * nao + mu) * (int64_t)nocc + i];
+      for (int j = 0; j < 8; ++j) {
+        const double2 p = *reinterpret_cast<const double2*>(src + 2 * j);
+        wd[2 * j] = digit_word(p.x, e);
+        wd[2 * j + 1] = digit_word(p.y, e);
       }
-      wd[j] = digit_word(v, e);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int k = kc * 16 + j;
+        wd[j] = (mu < nao && k < kb) ? digit_word(src[j], e) : 0ull;
+      }
     }
     int8_t* dst = Xd + ((int64_t)b * nao_pad + mu) * kbp + kc * 16;
 #pragma unroll
@@ -201,21 +296,41 @@ __device__ __forceinline__ void lower_tile(int idx, int& t1, int& t2) {
 // ---------------------------------------------------------------------------
 // K partials: Kp[grp][mu][nu] = sum over blocks b of group grp (ascending) of
 // recombine(S_g of X_b X_b^T), on lower 64x64 tiles; 4 waves x (32 x 32).
+// Per 64-wide k step the two row panels (S planes x 64 rows x 64 B each; one
+// panel on diagonal tiles) are staged in LDS by the whole workgroup; the next
+// step's panels are prefetched into registers while the current step runs.
 // ---------------------------------------------------------------------------
 template <int S>
 __global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
                                                 const int32_t* __restrict__ F, int nb, int nao,
                                                 int nao_pad, int kbp, int groups,
                                                 double* __restrict__ Kp) {
+  constexpr int ROW = 80;  // 64 B + 16 B pad: conflict-free 16-byte fragment reads
+  __shared__ __attribute__((aligned(16))) int8_t Ls[2][S][64][ROW];
   int t1, t2;
   lower_tile(blockIdx.x, t1, t2);
+  const bool diag = t1 == t2;
   const int grp = blockIdx.y;
   const int b_lo = (int)((int64_t)grp * nb / groups);
   const int b_hi = (int)((int64_t)(grp + 1) * nb / groups);
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const int rbase = t1 * 64 + (w >> 1) * 32;
-  const int cbase = t2 * 64 + (w & 1) * 32;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int64_t plane = (int64_t)nb * nao_pad * kbp;
+  const int ksteps = kbp >> 6;
+  // loader: thread t moves row t/4, 16-byte part t%4 of every plane of both panels
+  const int lrow = t >> 2, lpart = t & 3;
+  const int8_t* srcA = Xd + (int64_t)(t1 * 64 + lrow) * kbp + lpart * 16;
+  const int8_t* srcB = Xd + (int64_t)(t2 * 64 + lrow) * kbp + lpart * 16;
+  const int ldst = lrow * ROW + lpart * 16;
+  i32x4 preA[S], preB[S];
+#define DFJK_K_LOAD_STEP(BB, K0)                                                               \
+  {                                                                                            \
+    const int64_t off_ = (int64_t)(BB) * nao_pad * kbp + (K0);                                 \
+    _Pragma("unroll") for (int a = 0; a < S; ++a)                                              \
+      preA[a] = *reinterpret_cast<const i32x4*>(srcA + a * plane + off_);                      \
+    _Pragma("unroll") for (int a = 0; a < S; ++a)                                              \
+      preB[a] = diag ? preA[a] : *reinterpret_cast<const i32x4*>(srcB + a * plane + off_);     \
+  }
 
   double kacc[2][2][4];
 #pragma unroll
@@ -225,6 +340,7 @@ __global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
 #pragma unroll
       for (int r = 0; r < 4; ++r) kacc[i][j][r] = 0.0;
 
+  if (b_lo < b_hi) DFJK_K_LOAD_STEP(b_lo, 0)
   for (int b = b_lo; b < b_hi; ++b) {
     i32x4 acc[S][2][2];
 #pragma unroll
@@ -233,43 +349,51 @@ __global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[g][i][j] = i32x4{0, 0, 0, 0};
-
-    const int8_t* xb = Xd + (int64_t)b * nao_pad * kbp;
-    const int8_t* ra0 = xb + (int64_t)(rbase + (l & 15)) * kbp + (l >> 4) * 16;
-    const int8_t* ra1 = ra0 + 16 * (int64_t)kbp;
-    const int8_t* ca0 = xb + (int64_t)(cbase + (l & 15)) * kbp + (l >> 4) * 16;
-    const int8_t* ca1 = ca0 + 16 * (int64_t)kbp;
-    for (int k0 = 0; k0 < kbp; k0 += 64) {
-      i32x4 af[S][2], bf[S][2];
+    for (int ks = 0; ks < ksteps; ++ks) {
+      __syncthreads();
 #pragma unroll
-      for (int a = 0; a < S; ++a) {
-        af[a][0] = *reinterpret_cast<const i32x4*>(ra0 + a * plane + k0);
-        af[a][1] = *reinterpret_cast<const i32x4*>(ra1 + a * plane + k0);
-        bf[a][0] = *reinterpret_cast<const i32x4*>(ca0 + a * plane + k0);
-        bf[a][1] = *reinterpret_cast<const i32x4*>(ca1 + a * plane + k0);
+      for (int a = 0; a < S; ++a) *reinterpret_cast<i32x4*>(&Ls[0][a][0][0] + ldst) = preA[a];
+#pragma unroll
+      for (int a = 0; a < S; ++a) *reinterpret_cast<i32x4*>(&Ls[1][a][0][0] + ldst) = preB[a];
+      __syncthreads();
+      {
+        const bool last = ks + 1 == ksteps;
+        const int nb_ = last ? b + 1 : b;
+        const int nk_ = last ? 0 : (ks + 1) * 64;
+        if (nb_ < b_hi) DFJK_K_LOAD_STEP(nb_, nk_)
       }
+      i32x4 bf[S][2];
 #pragma unroll
-      for (int a = 0; a < S; ++a)
+      for (int bb = 0; bb < S; ++bb)
 #pragma unroll
-        for (int bb = 0; bb < S - a; ++bb)
+        for (int j = 0; j < 2; ++j)
+          bf[bb][j] = *reinterpret_cast<const i32x4*>(&Ls[1][bb][wc + j * 16 + r16][q * 16]);
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) {
+        i32x4 af[S];
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+          af[a] = *reinterpret_cast<const i32x4*>(&Ls[0][a][wr + i * 16 + r16][q * 16]);
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+          for (int bb = 0; bb < S - a; ++bb)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-              acc[a + bb][i][j] =
-                  __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a][i], bf[bb][j], acc[a + bb][i][j], 0, 0, 0);
+              acc[a + bb][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[bb][j],
+                                                                      acc[a + bb][i][j], 0, 0, 0);
+      }
     }
+    // end of aux block b: recombine into the FP64 partial sum
     const int32_t* Fb = F + (int64_t)b * nao_pad;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const int nu = cbase + j * 16 + (l & 15);
-        const int fn = Fb[nu];
+        const int fn = Fb[t2 * 64 + wc + j * 16 + r16];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int mu = rbase + i * 16 + (l >> 4) * 4 + r;
-          const int base = Fb[mu] + fn + 4;
+          const int base = Fb[t1 * 64 + wr + i * 16 + q * 4 + r] + fn + 4;
           double z = 0.0;
 #pragma unroll
           for (int g = S + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][i][j][r], base - 8 * g);
@@ -278,15 +402,16 @@ __global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
       }
   }
 
+#undef DFJK_K_LOAD_STEP
   double* out = Kp + (int64_t)grp * nao * nao;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int nu = cbase + j * 16 + (l & 15);
+      const int nu = t2 * 64 + wc + j * 16 + r16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int mu = rbase + i * 16 + (l >> 4) * 4 + r;
+        const int mu = t1 * 64 + wr + i * 16 + q * 4 + r;
         if (mu < nao && nu < nao) out[(int64_t)mu * nao + nu] = kacc[i][j][r];
       }
     }
@@ -342,41 +467,59 @@ __global__ __launch_bounds__(64) void k_debug_pairs(const int8_t* __restrict__ A
   }
 }
 
+template <int S, bool FULLK, int KSUB>
+hipError_t launch_x_sk(hipStream_t st, const double* B, int64_t M, int nao, const int32_t* b_exp,
+                       const int8_t* dC, int ncp, int kp, const int32_t* f_col, int nocc,
+                       double* X, int xlayout, unsigned long long* xmax, int pblk, const double* D,
+                       double* rowdot) {
+  const unsigned gx = (unsigned)((M + 63) / 64);
+  if (ncp % 96 == 0) {
+    hipLaunchKernelGGL((k_x_int8<S, 6, FULLK, KSUB>), dim3(gx, ncp / 96), dim3(512), 0, st, B, M,
+                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot);
+  } else if (ncp % 64 == 0) {
+    hipLaunchKernelGGL((k_x_int8<S, 4, FULLK, KSUB>), dim3(gx, ncp / 64), dim3(512), 0, st, B, M,
+                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot);
+  } else {
+    hipLaunchKernelGGL((k_x_int8<S, 2, FULLK, KSUB>), dim3(gx, ncp / 32), dim3(512), 0, st, B, M,
+                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot);
+  }
+  return hipGetLastError();
+}
+
+// Chunks of 128 k (two MFMA k steps, twice the bytes in flight per load) where
+// the registers allow it (s <= 5) and nao is a multiple of 128.
 template <int S>
 hipError_t launch_x_s(hipStream_t st, const double* B, int64_t M, int nao, const int32_t* b_exp,
                       const int8_t* dC, int ncp, int kp, const int32_t* f_col, int nocc,
-                      double* X, unsigned long long* xmax, int pblk) {
-  const unsigned gx = (unsigned)((M + 63) / 64);
-  if (ncp % 96 == 0) {
-    hipLaunchKernelGGL((k_x_int8<S, 6>), dim3(gx, ncp / 96), dim3(256), 0, st, B, M, nao, b_exp,
-                       dC, ncp, kp, f_col, nocc, X, xmax, nao, pblk);
-  } else if (ncp % 64 == 0) {
-    hipLaunchKernelGGL((k_x_int8<S, 4>), dim3(gx, ncp / 64), dim3(256), 0, st, B, M, nao, b_exp,
-                       dC, ncp, kp, f_col, nocc, X, xmax, nao, pblk);
-  } else {
-    hipLaunchKernelGGL((k_x_int8<S, 2>), dim3(gx, ncp / 32), dim3(256), 0, st, B, M, nao, b_exp,
-                       dC, ncp, kp, f_col, nocc, X, xmax, nao, pblk);
-  }
-  return hipGetLastError();
+                      double* X, int xlayout, unsigned long long* xmax, int pblk, const double* D,
+                      double* rowdot) {
+  if (S <= 5 && nao % 128 == 0)
+    return launch_x_sk<S, true, (S <= 5 ? 2 : 1)>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X,
+                                                   xlayout, xmax, pblk, D, rowdot);
+  if (nao % 64 == 0)
+    return launch_x_sk<S, true, 1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax,
+                                   pblk, D, rowdot);
+  return launch_x_sk<S, false, 1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax,
+                                  pblk, D, rowdot);
 }
 
 }  // namespace
 
 hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, int nao,
                          const int32_t* b_exp, const int8_t* dC, int ncp, int kp,
-                         const int32_t* f_col, int nocc, double* X, unsigned long long* xmax,
-                         int pblk) {
+                         const int32_t* f_col, int nocc, double* X, int xlayout,
+                         unsigned long long* xmax, int pblk, const double* D, double* rowdot) {
   const int64_t M = naux * nao;
   if (M <= 0 || nocc <= 0) return hipSuccess;
   switch (s) {
-    case 1: return launch_x_s<1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xmax, pblk);
-    case 2: return launch_x_s<2>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xmax, pblk);
-    case 3: return launch_x_s<3>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xmax, pblk);
-    case 4: return launch_x_s<4>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xmax, pblk);
-    case 5: return launch_x_s<5>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xmax, pblk);
-    case 6: return launch_x_s<6>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xmax, pblk);
-    case 7: return launch_x_s<7>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xmax, pblk);
-    case 8: return launch_x_s<8>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xmax, pblk);
+    case 1: return launch_x_s<1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
+    case 2: return launch_x_s<2>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
+    case 3: return launch_x_s<3>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
+    case 4: return launch_x_s<4>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
+    case 5: return launch_x_s<5>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
+    case 6: return launch_x_s<6>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
+    case 7: return launch_x_s<7>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
+    case 8: return launch_x_s<8>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
     default: return hipErrorInvalidValue;
   }
 }

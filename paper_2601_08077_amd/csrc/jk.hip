@@ -98,23 +98,53 @@ __global__ void k_k_reduce(const double* __restrict__ Kp, int groups, int nao, d
   }
 }
 
-// energies[0] = 1/2 sum_P rho_P^2, energies[1] = -1/4 sum D K (one workgroup).
-__global__ __launch_bounds__(256) void k_energies(const double* __restrict__ rho, int64_t naux,
-                                                  const double* __restrict__ D,
-                                                  const double* __restrict__ K, int64_t nn,
-                                                  double* __restrict__ energies) {
+// Energies in two deterministic passes: 256 workgroups reduce fixed slices of
+// rho^2 and D*K into scratch[2][256]; one workgroup then sums the partials in
+// order.  energies[0] = 1/2 sum_P rho_P^2, energies[1] = -1/4 sum D K.
+__global__ __launch_bounds__(256) void k_energy_partials(const double* __restrict__ rho,
+                                                         int64_t naux,
+                                                         const double* __restrict__ D,
+                                                         const double* __restrict__ K, int64_t nn,
+                                                         double* __restrict__ scratch) {
+  __shared__ double sh[4];
+  const int t = threadIdx.x, g = blockIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = (int64_t)g * 256 + t; i < naux; i += stride) a = fma(rho[i], rho[i], a);
+  for (int64_t i = (int64_t)g * 256 + t; i < nn; i += stride) b = fma(D[i], K[i], b);
+  const double sa = block_sum_256(a, sh);
+  const double sb = block_sum_256(b, sh);
+  if (t == 0) {
+    scratch[g] = sa;
+    scratch[256 + g] = sb;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__ scratch,
+                                                      double* __restrict__ energies) {
   __shared__ double sh[4];
   const int t = threadIdx.x;
-  double a = 0.0;
-  for (int64_t i = t; i < naux; i += 256) a = fma(rho[i], rho[i], a);
-  const double ej = block_sum_256(a, sh);
-  double b = 0.0;
-  for (int64_t i = t; i < nn; i += 256) b = fma(D[i], K[i], b);
-  const double ex = block_sum_256(b, sh);
+  const double ej = block_sum_256(scratch[t], sh);
+  const double ex = block_sum_256(scratch[256 + t], sh);
   if (t == 0) {
     energies[0] = 0.5 * ej;
     energies[1] = -0.25 * ex;
   }
+}
+
+// rho_P = sum_mu rowdot[P nao + mu], one wavefront per P, fixed lane order.
+__global__ __launch_bounds__(256) void k_rho_reduce(const double* __restrict__ rowdot,
+                                                    int64_t naux, int nao,
+                                                    double* __restrict__ rho) {
+  const int lane = threadIdx.x & 63;
+  const int64_t P = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  if (P >= naux) return;
+  const double* r = rowdot + P * nao;
+  double a = 0.0;
+  for (int mu = lane; mu < nao; mu += 64) a += r[mu];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off);
+  if (lane == 0) rho[P] = a;
 }
 
 // Per (block, mu): A = nao kappa1 Fsum sum_{P in b} 2^e_B, dmax = nao kappa1 Fmax
@@ -220,9 +250,18 @@ hipError_t launch_k_reduce(hipStream_t st, const double* Kp, int groups, int nao
 }
 
 hipError_t launch_energies(hipStream_t st, const double* rho, int64_t naux, const double* D,
-                           const double* K, int nao, double* energies) {
-  hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, st, rho, naux, D, K, (int64_t)nao * nao,
-                     energies);
+                           const double* K, int nao, double* scratch, double* energies) {
+  hipLaunchKernelGGL(k_energy_partials, dim3(256), dim3(256), 0, st, rho, naux, D, K,
+                     (int64_t)nao * nao, scratch);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, scratch, energies);
+  return hipGetLastError();
+}
+
+hipError_t launch_rho_reduce(hipStream_t st, const double* rowdot, int64_t naux, int nao,
+                             double* rho) {
+  if (naux <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rho_reduce, dim3((unsigned)((naux + 3) / 4)), dim3(256), 0, st, rowdot,
+                     naux, nao, rho);
   return hipGetLastError();
 }
 

@@ -29,20 +29,24 @@ __global__ __launch_bounds__(256) void k_row_exp(const double* __restrict__ A, i
 }
 
 // f[i] = exponent of max_nu |C[nu][i]| (the columns of C are the rows of the
-// right operand of Eq. 5 over its contraction index nu).
-__global__ void k_col_exp(const double* __restrict__ C, int64_t nao, int64_t nocc,
-                          int32_t* __restrict__ f, int* status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// right operand of Eq. 5 over its contraction index nu): one wavefront per column.
+__global__ __launch_bounds__(256) void k_col_exp(const double* __restrict__ C, int64_t nao,
+                                                 int64_t nocc, int32_t* __restrict__ f,
+                                                 int* status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (i >= nocc) return;
   double m = 0.0;
   bool bad = false;
-  for (int64_t k = 0; k < nao; ++k) {
+  for (int64_t k = lane; k < nao; k += kWave) {
     const double v = C[k * nocc + i];
     bad |= !isfinite(v);
     m = fmax(m, fabs(v));
   }
-  if (bad) atomicOr(status, kStatusNonFinite);
-  f[i] = exp_of_max(m);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if (__any(bad) && lane == 0) atomicOr(status, kStatusNonFinite);
+  if (lane == 0) f[i] = exp_of_max(m);
 }
 
 // digits[a][r][c] for a = 0..s-1 (a = 0 is d_1).
@@ -110,7 +114,7 @@ hipError_t launch_row_exp(hipStream_t st, const double* A, int64_t rows, int64_t
 hipError_t launch_col_exp(hipStream_t st, const double* C, int64_t nao, int64_t nocc,
                           int32_t* f, int* status) {
   if (nocc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_col_exp, dim3(grid_for(nocc, 64)), dim3(64), 0, st, C, nao, nocc, f,
+  hipLaunchKernelGGL(k_col_exp, dim3(grid_for(nocc * 64, 256)), dim3(256), 0, st, C, nao, nocc, f,
                      status);
   return hipGetLastError();
 }
