@@ -340,3 +340,86 @@ def emulated_build_jk(B, C, s, occ=2.0, D=None, pblk=64, groups=1):
     bound = k_error_bound(e_B, f_C, F, s, occ=occ, pblk=pblk) if s else None
     return dict(rho=rho, J=J, X=X, K=K, e_j=e_j, e_x=e_x, D=D,
                 e_B=e_B, f_C=f_C, F=F, bound=bound)
+
+
+# ----------------------------------------------------------------------------
+# Sliced Coulomb part: rho and J from the digits of B (FP64 only in the
+# recombination and the energies)
+# ----------------------------------------------------------------------------
+def emulated_rho(B, D, s):
+    """rho_P = sum over mu (ascending, FP64) of the emulated row dot
+    r[P, mu] = sum_nu B[P, mu, nu] D[mu, nu]: rows (P, mu) of B and rows mu of D
+    sliced over nu, pairs a + b <= s + 1, recombined with exponent
+    e_B[P, mu] + g[mu].  Returns (rho, r, e_B, g)."""
+    B = np.asarray(B, dtype=np.float64)
+    naux, nao, _ = B.shape
+    dB, e_B = slice_rows(B.reshape(naux * nao, nao), s)
+    dD, g = slice_rows(D, s)
+    S = np.zeros((s, naux * nao), dtype=np.int64)
+    for a, b in pairs(s):
+        prod = dB[a - 1].astype(np.float64).reshape(naux, nao, nao) * dD[b - 1].astype(np.float64)[None]
+        S[a + b - 2] += np.rint(prod.sum(axis=2)).astype(np.int64).reshape(-1)
+    e_rows = e_B + np.tile(g, naux)
+    r = recombine(S[:, :, None], e_rows, np.zeros(1, dtype=np.int64), s)[:, 0].reshape(naux, nao)
+    rho = np.zeros(naux)
+    for mu in range(nao):
+        rho = rho + r[:, mu]
+    return rho, r, e_B.reshape(naux, nao), g
+
+
+def emulated_j(B, rho, s, e_B=None):
+    """J[mu, nu] = sum_P rho_P B[P, mu, nu] emulated for mu >= nu, mirrored.
+
+    With w[P, mu] = ldexp(rho_P, e_B[P, mu]) and B~ = B / 2^e_B (whose digits
+    are the digits of B's rows (P, mu) over nu, weights 2^(2 - 8a)), J[mu, nu]
+    = sum_P w[P, mu] B~[P, mu, nu]: w's column mu is sliced over P (exponent
+    h_mu), B~ enters with exponent 0.  Returns (J, h)."""
+    B = np.asarray(B, dtype=np.float64)
+    naux, nao, _ = B.shape
+    dB, eb = slice_rows(B.reshape(naux * nao, nao), s)
+    e_B = eb.reshape(naux, nao) if e_B is None else e_B
+    w = np.ldexp(np.asarray(rho, dtype=np.float64)[:, None], e_B.astype(np.int32))
+    dW, h = slice_rows(w.T, s)                      # (s, nao, naux)
+    dB = dB.reshape(s, naux, nao, nao)
+    S = np.zeros((s, nao, nao), dtype=np.int64)
+    for a, b in pairs(s):                           # a: digit of w, b: digit of B~
+        S[a + b - 2] += np.rint(np.einsum("mp,pmn->mn", dW[a - 1].astype(np.float64),
+                                          dB[b - 1].astype(np.float64))).astype(np.int64)
+    Jfull = recombine(S, h, np.zeros(nao, dtype=np.int64), s)
+    J = np.tril(Jfull)
+    J = J + np.tril(J, -1).T
+    return J, h
+
+
+def coulomb_error_bound(B_exp, g, h, r, D, rho, s, naux, nao):
+    """Bound on max |J_hat - J| (mu >= nu, mirrored) for the sliced Coulomb part.
+
+    rho: each row dot is an emulated product over nao terms with exponents
+    e_B + g (kappa_s(nao)), plus the (nao - 1) roundings of the mu sum;
+    J: an emulated product over naux terms with exponents h_mu and 0, plus
+    the propagated rho error sum_P d_rho_P 2^e_B[P, mu]."""
+    eB = np.exp2(np.asarray(B_exp, dtype=np.float64))
+    d_r = nao * eB * np.exp2(np.asarray(g, dtype=np.float64))[None, :] * kappa(s, nao)
+    d_rho = d_r.sum(axis=1) + (nao - 1) * UNIT_ROUNDOFF * (1 + UNIT_ROUNDOFF) ** nao \
+        * np.abs(r).sum(axis=1)
+    prop = (d_rho[:, None] * eB).sum(axis=0)        # per mu
+    own = naux * np.exp2(np.asarray(h, dtype=np.float64)) * kappa(s, naux)
+    return float(np.max(own + prop))
+
+
+def sliced_build_jk(B, C, s, occ=2.0, D=None, pblk=64, groups=1):
+    """The sliced mode: X and K as in ``emulated_build_jk``, rho and J from
+    the digits of B.  Returns the same keys plus j_bound."""
+    B = np.asarray(B, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    if D is None:
+        D = occ * (C @ C.T)
+    out = emulated_build_jk(B, C, s, occ=occ, D=D, pblk=pblk, groups=groups)
+    rho, r, e_B, g = emulated_rho(B, D, s)
+    J, h = emulated_j(B, rho, s, e_B)
+    from . import jk as _jk
+    e_j, e_x = _jk.energies(rho, D, out["K"])
+    naux, nao, _ = B.shape
+    out.update(rho=rho, J=J, e_j=e_j, e_x=e_x,
+               j_bound=coulomb_error_bound(e_B, g, h, r, D, rho, s, naux, nao))
+    return out

@@ -248,3 +248,42 @@ def test_block_groups_partition_and_order(prob):
     assert np.all(np.abs(b["K"] - ref) <= b["bound"])
     assert np.abs(a["K"] - b["K"]).max() <= 16 * 2.0 ** -53 * np.abs(a["K"]).max()
     assert np.array_equal(b["K"], b["K"].T)
+
+
+# -- sliced Coulomb part (rho and J from the digits of B) -------------------------
+@pytest.mark.parametrize("s", range(1, 9))
+def test_sliced_coulomb_within_bound(prob, s):
+    ref = jk.build_jk(prob["B"], prob["C"], occ=2.0)
+    out = em.sliced_build_jk(prob["B"], prob["C"], s, occ=2.0)
+    assert np.array_equal(out["J"], out["J"].T)
+    err = np.abs(out["J"] - ref["J"]).max()
+    assert err <= out["j_bound"]
+    assert err / np.linalg.norm(ref["J"]) <= 64 * 2.0 ** -(8 * s - 1) + 2e-15
+    # K is the emulated K of the plain sliced path (unchanged by the Coulomb mode)
+    emu = em.emulated_build_jk(prob["B"], prob["C"], s, occ=2.0)
+    assert np.array_equal(out["K"], emu["K"])
+
+
+def test_sliced_rho_integer_inputs_exact():
+    # integer B rows and D rows whose maxima lie in [32, 63] are single digits of
+    # weight 1: level 1 gives the exact integer row dots and rho
+    rng = np.random.default_rng(8)
+    naux, nao = 5, 12
+    B = rng.integers(-63, 64, size=(naux, nao, nao)).astype(np.float64)
+    B = np.triu(B) + np.triu(B, 1).transpose(0, 2, 1)
+    for P in range(naux):
+        np.fill_diagonal(B[P], 50.0)
+    D = rng.integers(-63, 64, size=(nao, nao)).astype(np.float64)
+    D = np.triu(D) + np.triu(D, 1).T
+    np.fill_diagonal(D, -40.0)
+    rho, r, _, _ = em.emulated_rho(B, D, 1)
+    exact = np.einsum("pmn,mn->pm", B, D)
+    assert np.array_equal(r, exact)
+    assert np.array_equal(rho, exact.sum(axis=1))
+
+
+def test_sliced_s8_reaches_fp64_floor(prob):
+    ref = jk.build_jk(prob["B"], prob["C"], occ=2.0)
+    out = em.sliced_build_jk(prob["B"], prob["C"], 8, occ=2.0)
+    assert np.abs(out["J"] - ref["J"]).max() <= 1e-14 * np.linalg.norm(ref["J"])
+    assert np.abs(out["rho"] - ref["rho"]).max() <= 1e-14 * np.abs(ref["rho"]).max()
