@@ -24,25 +24,18 @@ __device__ __forceinline__ int exp_of_max(double m) {
 
 // Balanced base-256 digits of N = trunc(a * 2^(62 - e)), |N| < 2^62, packed in
 // one word: byte 7 holds d_1 (most significant, |d_1| <= 64), byte 0 holds d_8.
-// N is built from the bits of a (exact truncation toward zero: the 53-bit
-// significand shifted by exponent(a) - 1075 + 62 - e, then the sign).  Adding
-// 0x80 to each of the seven low bytes and flipping their top bit turns the
-// two's-complement bytes of N into the balanced digits in [-128, 127] (each low
-// byte u becomes u - 128 once the carries of the +0x80 have moved up).
-// Requires |a| < 2^e (e is the exponent of the row maximum).
+// N is formed exactly in FP64 (power-of-two scaling, trunc) and split into its
+// high and low 32-bit halves (floor of y / 2^32, then the exact remainder).
+// Adding 0x80 to each of the seven low bytes and flipping their top bit turns
+// the two's-complement bytes of N into the balanced digits in [-128, 127]
+// (each low byte u becomes u - 128 once the carries of the +0x80 have moved
+// up).  Requires |a| < 2^e (e is the exponent of the row maximum).
 __device__ __forceinline__ uint64_t digit_word(double a, int e) {
-  const unsigned long long bits = (unsigned long long)__double_as_longlong(a);
-  const int be = (int)((bits >> 52) & 0x7ff);
-  const unsigned long long frac = bits & 0x000fffffffffffffull;
-  const unsigned long long mant = be ? (frac | 0x0010000000000000ull) : frac;
-  const int sh = (be ? be : 1) - 1013 - e;  // shift of the significand into N (<= 9)
-  // branch-free: both shifts, then selects (shift counts taken mod 64)
-  const unsigned long long left = mant << (sh & 63);
-  const unsigned long long right = mant >> ((-sh) & 63);
-  unsigned long long mag = sh >= 0 ? left : right;
-  mag = sh <= -64 ? 0ull : mag;
-  const unsigned long long neg = 0ull - (bits >> 63);  // all ones when a < 0
-  const unsigned long long n = (mag ^ neg) - neg;
+  const double y = trunc(ldexp(a, 62 - e));
+  const double yh = floor(y * 0x1p-32);
+  const double yl = fma(-yh, 0x1p32, y);
+  const unsigned long long n =
+      ((unsigned long long)(unsigned int)(int)yh << 32) | (unsigned long long)(unsigned int)yl;
   const unsigned long long bias = 0x0080808080808080ull;
   return (n + bias) ^ bias;
 }
