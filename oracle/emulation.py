@@ -281,7 +281,8 @@ def emulated_k(X, s, occ=2.0, pblk=64, groups=1):
 
 
 def k_error_bound(e_B, f_C, F, s, occ=2.0, pblk=64, nocc=None):
-    """Elementwise bound on |K_hat - K| for the emulated pipeline (s >= 1).
+    """Elementwise bound on |K_hat - K| for the emulated pipeline: s one slice
+    count (>= 1) or one per block (0 = an FP64 block: gamma factors).
 
     K1 error per X element: dX[P,mu,i] <= nao 2^(e_B[P,mu] + f_C[i]) kappa.
     Within block b, with |X_hat[P,mu,i]| < 2^F[b,mu]:
@@ -296,19 +297,20 @@ def k_error_bound(e_B, f_C, F, s, occ=2.0, pblk=64, nocc=None):
     naux, nao = e_B.shape
     nocc = f_C.shape[0] if nocc is None else nocc
     blocks = block_ranges(naux, pblk)
-    kap1 = kappa(s, nao)
+    s_of = (lambda bi: int(s[bi])) if np.ndim(s) else (lambda bi: int(s))
     Fsum = np.sum(np.exp2(f_C))
     Fmax = np.exp2(np.max(f_C)) if nocc else 0.0
     bound = np.zeros((nao, nao))
     kabs = np.zeros((nao, nao))
     for bi, (p0, p1) in enumerate(blocks):
         kb = (p1 - p0) * nocc
+        kap1 = kappa(s_of(bi), nao)
         eb = np.exp2(e_B[p0:p1])                       # (|b|, nao)
         A = nao * kap1 * Fsum * np.sum(eb, axis=0)     # (nao,)
         dmax = nao * kap1 * Fmax * np.max(eb, axis=0)  # (nao,)
         pf = np.exp2(np.asarray(F[bi], dtype=np.float64))
         prop = A[:, None] * pf[None, :] + (pf[:, None] + dmax[:, None]) * A[None, :]
-        kap2 = kappa(s, kb)
+        kap2 = kappa(s_of(bi), kb)
         emu2 = kb * np.outer(pf, pf) * kap2
         bound += prop + emu2
         kabs += kb * np.outer(pf, pf) * (1.0 + kap2)
@@ -340,6 +342,54 @@ def emulated_build_jk(B, C, s, occ=2.0, D=None, pblk=64, groups=1):
     bound = k_error_bound(e_B, f_C, F, s, occ=occ, pblk=pblk) if s else None
     return dict(rho=rho, J=J, X=X, K=K, e_j=e_j, e_x=e_x, D=D,
                 e_B=e_B, f_C=f_C, F=F, bound=bound)
+
+
+# ----------------------------------------------------------------------------
+# Per-block slice counts (the learned controller's decisions)
+# ----------------------------------------------------------------------------
+def emulated_build_jk_blocks(B, C, s_blocks, occ=2.0, D=None, pblk=64):
+    """The emulated build with its own slice count s_b per aux block b (0 = FP64
+    for that block): X_b = emu(B_b C) at s_b, K_b = emu(X_b X_b^T) at s_b,
+    K = occ * sum_b K_b with b ascending; rho and J in FP64.  The K bound is
+    ``k_error_bound`` with each block's own factors.  Blocks with s_b = 0 use
+    NumPy's FP64 products (equal to a GPU FP64 product only up to rounding)."""
+    from . import jk as _jk
+    B = np.asarray(B, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    naux, nao, _ = B.shape
+    nocc = C.shape[1]
+    blocks = block_ranges(naux, pblk)
+    s_blocks = [int(v) for v in s_blocks]
+    if len(s_blocks) != len(blocks):
+        raise ValueError("one slice count per aux block")
+    if D is None:
+        D = occ * (C @ C.T)
+    rho = _jk.rho_of(B, D)
+    J = _jk.j_of(B, rho)
+    X = np.zeros((naux, nao, nocc))
+    e_B = row_exponents(B.reshape(naux * nao, nao)).reshape(naux, nao)
+    f_C = row_exponents(C.T)
+    F = np.zeros((len(blocks), nao), dtype=np.int64)
+    Kacc = np.zeros((nao, nao))
+    for bi, (p0, p1) in enumerate(blocks):
+        sb = s_blocks[bi]
+        if sb == 0:
+            X[p0:p1] = np.einsum("pmn,ni->pmi", B[p0:p1], C)
+        else:
+            X[p0:p1] = emulated_x(B[p0:p1], C, sb)[0]
+        Xb = x_block(X, p0, p1)
+        F[bi] = row_exponents(Xb)
+        if sb == 0:
+            Kb = Xb @ Xb.T
+        else:
+            dX, _ = slice_rows(Xb, sb)
+            Kb = recombine(slice_products(dX, dX.transpose(0, 2, 1), sb), F[bi], F[bi], sb)
+        Kacc = Kacc + Kb
+    K = occ * Kacc
+    e_j, e_x = _jk.energies(rho, D, K)
+    bound = k_error_bound(e_B, f_C, F, s_blocks, occ=occ, pblk=pblk)
+    return dict(rho=rho, J=J, X=X, K=K, e_j=e_j, e_x=e_x, D=D, e_B=e_B, f_C=f_C, F=F,
+                bound=bound)
 
 
 # ----------------------------------------------------------------------------

@@ -287,3 +287,39 @@ def test_sliced_s8_reaches_fp64_floor(prob):
     out = em.sliced_build_jk(prob["B"], prob["C"], 8, occ=2.0)
     assert np.abs(out["J"] - ref["J"]).max() <= 1e-14 * np.linalg.norm(ref["J"])
     assert np.abs(out["rho"] - ref["rho"]).max() <= 1e-14 * np.abs(ref["rho"]).max()
+
+
+# ------------------------------------------------------------ per-block slice counts
+def test_block_slice_counts_uniform_equal_plain_build():
+    p = dfinputs.make_problem(nao=20, naux=50, nocc=5, L=4.0, seed=4, row_scale=True)
+    nb = 4  # pblk 16: blocks 16, 16, 16, 2
+    for s in (2, 5):
+        a = em.emulated_build_jk_blocks(p["B"], p["C"], [s] * nb, D=p["D"], pblk=16)
+        b = em.emulated_build_jk(p["B"], p["C"], s, D=p["D"], pblk=16, groups=nb)
+        assert np.array_equal(a["K"], b["K"])
+        assert np.array_equal(a["X"], b["X"])
+        assert np.allclose(a["bound"], b["bound"], rtol=1e-14, atol=0)
+
+
+def test_block_slice_counts_mixed_within_bound_and_fp64_blocks():
+    p = dfinputs.make_problem(nao=20, naux=50, nocc=5, L=4.0, seed=5, row_scale=True)
+    K64 = jk.build_jk(p["B"], p["C"], D=p["D"])["K"]
+    for sb in ([1, 3, 6, 8], [0, 2, 0, 4], [0, 0, 0, 0]):
+        r = em.emulated_build_jk_blocks(p["B"], p["C"], sb, D=p["D"], pblk=16)
+        assert np.all(np.abs(r["K"] - K64) <= r["bound"])
+        assert np.array_equal(r["K"], r["K"].T)
+    # all-FP64 blocks: K = occ sum_b X_b X_b^T in FP64, the bound is rounding-sized
+    r = em.emulated_build_jk_blocks(p["B"], p["C"], [0, 0, 0, 0], D=p["D"], pblk=16)
+    assert np.max(r["bound"]) / np.linalg.norm(K64) < 1e-12
+
+
+def test_block_slice_count_only_moves_its_block():
+    # raising one block's s changes K by at most that block's own error terms
+    p = dfinputs.make_problem(nao=16, naux=48, nocc=4, L=4.0, seed=6, row_scale=False)
+    lo = em.emulated_build_jk_blocks(p["B"], p["C"], [2, 2, 2], D=p["D"], pblk=16)
+    hi = em.emulated_build_jk_blocks(p["B"], p["C"], [2, 8, 2], D=p["D"], pblk=16)
+    assert np.array_equal(lo["X"][:16], hi["X"][:16])
+    assert np.array_equal(lo["X"][32:], hi["X"][32:])
+    assert not np.array_equal(lo["X"][16:32], hi["X"][16:32])
+    K64 = jk.build_jk(p["B"], p["C"], D=p["D"])["K"]
+    assert np.abs(hi["K"] - K64).max() < np.abs(lo["K"] - K64).max()
