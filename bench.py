@@ -164,6 +164,8 @@ def main():
     ap.add_argument("--sweep-reps", type=int, default=5)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sliced", action="store_true",
+                    help="skip the sliced-mode levels (B as digit planes, digit rho and J)")
     ap.add_argument("--cpu-aux", type=int, default=64)
     ap.add_argument("--workload", choices=("jk", "adaptive"), default="jk",
                     help="jk: one J/K build per step (default); adaptive: the 20-iteration "
@@ -214,10 +216,10 @@ def main():
     def build():
         ctx.df_build_jk(B, be, C, 2.0, D, J, K, en, eb)
 
-    def timed(s, steps, warmup, stages=False):
+    def timed(s, steps, warmup, stages=False, fn=build):
         ctx.df_set_precision(s)
         for _ in range(warmup):
-            build()
+            fn()
         torch.cuda.synchronize()
         if stages:
             ctx.df_timing_begin(steps)
@@ -225,7 +227,7 @@ def main():
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record()
         for _ in range(steps):
-            build()
+            fn()
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / steps
@@ -242,7 +244,9 @@ def main():
     log("FP64 MFMA build")
     ms64, st64 = timed(0, max(3, args.steps // 2), 1, stages=True)
     K64 = K.clone()
+    J64 = J.clone()
     nK = float(torch.linalg.norm(K64))
+    nJ = float(torch.linalg.norm(J64))
     log(f"FP64: {ms64:.3f} ms/step")
 
     sweep = []
@@ -257,6 +261,39 @@ def main():
                           "bound_rel_fro": float(eb[0]) / nK,
                           "stages_ms": {k: round(v, 4) for k, v in st.items()}})
             log(f"s={s}: {ms:.3f} ms  maxabs/|K|F {sweep[-1]['maxabs_rel_fro']:.2e}")
+
+    # sliced mode: B held as 8 digit planes (prepared once), rho and J from digits
+    sliced = []
+    sliced_prep_ms = None
+    if not args.no_sliced:
+        from paper_2601_08077_amd.binding import df_prepare_b_size
+        planes = 8
+        dig = torch.empty(df_prepare_b_size(naux, nao, planes), dtype=torch.int8, device="cuda")
+        be2 = torch.empty_like(be)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.df_prepare_b(B, planes, be2, dig)
+        e1.record()
+        torch.cuda.synchronize()
+        assert ctx.df_get_status() == 0
+        sliced_prep_ms = e0.elapsed_time(e1)
+        eb2 = torch.empty(2, dtype=torch.float64, device="cuda")
+
+        def build_sliced():
+            ctx.df_build_jk_sliced(dig, planes, be2, naux, nao, C, 2.0, D, J, K, en, eb2)
+
+        for s_ in (3, 4, 5, 6, 7, 8):
+            ms, st = timed(s_, args.sweep_reps, 1, stages=True, fn=build_sliced)
+            sliced.append({"slices": s_, "ms": ms, "eff_tflops": F / ms / 1e9,
+                           "speedup_vs_fp64": ms64 / ms,
+                           "k_maxabs_rel_fro": float((K - K64).abs().max()) / nK,
+                           "j_maxabs_rel_fro": float((J - J64).abs().max()) / nJ,
+                           "k_bound_rel_fro": float(eb2[0]) / nK,
+                           "j_bound_rel_fro": float(eb2[1]) / nJ,
+                           "stages_ms": {k: round(v, 4) for k, v in st.items()}})
+            log(f"sliced s={s_}: {ms:.3f} ms  J maxabs/|J|F {sliced[-1]['j_maxabs_rel_fro']:.2e}")
+        del dig
 
     # headline: timed region of exactly --steps builds
     s = args.slices
@@ -299,6 +336,7 @@ def main():
         "roofline": roof,
         "roofline_stages": others,
         "sweep": sweep,
+        "sliced_mode": {"prepare_b_ms": sliced_prep_ms, "planes": 8, "levels": sliced},
     }
     if not args.no_cpu:
         log(f"cpu baseline: oracle on {args.cpu_aux} aux rows")

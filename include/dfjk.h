@@ -23,7 +23,9 @@
  *     in int32, one accumulator per anti-diagonal g = a + b;
  *   - FP64 recombination: Z = sum_{g = s+1 .. 2} ldexp(S_g, e_r + f_c + 4 - 8g),
  *     smallest weight first.
- * J and rho are FP64 in both modes (Sec. 3, first bullet: J stays FP64).
+ * In df_build_jk, J and rho are FP64 at every precision (the paper keeps J in
+ * FP64, Sec. 3).  The sliced mode (df_prepare_b / df_build_jk_sliced) also
+ * forms rho and J from the INT8 digits of B, with FP64 recombination.
  *
  * Conventions for every entry point:
  *   - Array arguments are DEVICE pointers to caller-owned memory (allocated by
@@ -76,6 +78,21 @@ void df_destroy(df_ctx* ctx);
 int df_set_precision(df_ctx* ctx, int slices);
 int df_get_precision(const df_ctx* ctx);
 
+/* Per-aux-block slice counts for df_build_jk (the learned controller's
+ * decisions; per-block precision extends the per-iteration rule of Sec. 3.2,
+ * Table 1, in the direction of Sec. 6): host_s[b] in 0..8 for each of the
+ * nblocks = ceil(naux / pblk) aux blocks, 0 = native FP64 for that block.
+ * X_b and K_b of block b are then formed at host_s[b]; each block gets its
+ * own K partial (the K group count becomes nblocks), summed in ascending
+ * block order; err_bound uses each block's own factors.  Set it before
+ * df_workspace_size.  The counts are copied (the call synchronises the
+ * context stream and may allocate a small device array owned by the
+ * context); host_s == NULL returns to the context precision for all blocks.
+ * df_build_x and df_build_jk_sliced do not take per-block counts
+ * (df_build_jk_sliced returns DF_EINVAL while they are set); df_build_jk
+ * returns DF_EINVAL when nblocks does not match its shape. */
+int df_set_block_precision(df_ctx* ctx, const int32_t* host_s, int64_t nblocks);
+
 /* Aux block size of the blocked K (Eqs. df-k-blk-1/2): 1..1024 (default 64). */
 int df_set_pblk(df_ctx* ctx, int pblk);
 
@@ -127,6 +144,38 @@ int df_build_x(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t n
 int df_build_jk(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t nao,
                 const int32_t* b_exp, const double* C, int64_t nocc, double occ,
                 const double* D, double* J, double* K, double* energies, double* err_bound);
+
+/* Sliced mode, step 1 (once per B; Sec. 3.2 splitting applied to B itself):
+ * b_exp[P*nao + mu] as in df_b_exponents and the first `planes` (1..8) digit
+ * planes of every row (P, mu) of B over nu:
+ *   b_dig[a][P*nao + mu][c], a = 0..planes-1 (a = 0 is d_1), c < ldk,
+ *   ldk = nao rounded up to a multiple of 64, columns c >= nao zero.
+ * df_prepare_b_size gives the byte count of b_dig (planes * naux * nao * ldk);
+ * b_dig must be 16-byte aligned.  Any prefix of the planes serves every level
+ * s <= planes.  Non-finite B sets the DF_ENONFINITE device status.  No
+ * workspace. */
+int df_prepare_b_size(int64_t naux, int64_t nao, int planes, size_t* bytes);
+int df_prepare_b(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t nao, int planes,
+                 int32_t* b_exp, int8_t* b_dig);
+
+/* Sliced mode, step 2: the build of df_build_jk (Eqs. 3-6) with every product
+ * over B taken from its digit planes at the context precision s
+ * (1 <= s <= planes; DF_EINVAL otherwise):
+ *   X = B C and K exactly as df_build_jk at level s (bitwise the same);
+ *   rho_P = sum over mu (ascending) of the emulated row dot
+ *     B[P][mu][:] . D[mu][:] (rows of D sliced over nu, s pairs rule);
+ *   J[mu][nu] (nu <= mu, mirrored) = emulated sum_P w[P][mu] B~[P][mu][nu]
+ *     with w[P][mu] = rho_P 2^b_exp[P*nao+mu], sliced over P for each mu, and
+ *     B~ = B / 2^b_exp (whose digits are b_dig).
+ * Arguments as df_build_jk, except b_dig / planes / b_exp from df_prepare_b
+ * (B itself is not read) and err_bound[2]: err_bound[0] bounds max |K - K_exact|,
+ * err_bound[1] bounds max |J - J_exact| (digit truncation, dropped pairs and
+ * the roundings of rho and of both recombinations).  Requires a workspace of
+ * df_workspace_size bytes. */
+int df_build_jk_sliced(df_ctx* ctx, const int8_t* b_dig, int planes, const int32_t* b_exp,
+                       int64_t naux, int64_t nao, const double* C, int64_t nocc, double occ,
+                       const double* D, double* J, double* K, double* energies,
+                       double* err_bound);
 
 /* Metric Cholesky (Sec. 2.1, Eq. 2): W [n][n] symmetric positive definite is
  * overwritten in place by L (lower triangle; the upper triangle is set to 0)

@@ -27,6 +27,7 @@ SIGNATURES = {
     "df_get_precision": (_int, [_c_void_p]),
     "df_set_pblk": (_int, [_c_void_p, _int]),
     "df_set_k_groups": (_int, [_c_void_p, _int]),
+    "df_set_block_precision": (_int, [_c_void_p, ctypes.POINTER(ctypes.c_int32), _i64]),
     "df_get_k_groups": (_int, [_c_void_p]),
     "df_workspace_size": (_int, [_c_void_p, _i64, _i64, _i64, _int, ctypes.POINTER(ctypes.c_size_t)]),
     "df_set_workspace": (_int, [_c_void_p, _c_void_p, ctypes.c_size_t]),
@@ -36,6 +37,11 @@ SIGNATURES = {
                           _c_void_p]),
     "df_build_jk": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _c_void_p, _c_void_p, _i64,
                            ctypes.c_double, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "df_prepare_b_size": (_int, [_i64, _i64, _int, ctypes.POINTER(ctypes.c_size_t)]),
+    "df_prepare_b": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _int, _c_void_p, _c_void_p]),
+    "df_build_jk_sliced": (_int, [_c_void_p, _c_void_p, _int, _c_void_p, _i64, _i64, _c_void_p,
+                                  _i64, ctypes.c_double, _c_void_p, _c_void_p, _c_void_p,
+                                  _c_void_p, _c_void_p]),
     "df_get_status": (_int, [_c_void_p]),
     "df_last_error": (ctypes.c_char_p, [_c_void_p]),
     "df_metric_cholesky": (_int, [_c_void_p, _c_void_p, _i64]),
@@ -125,6 +131,15 @@ class Context:
     def df_set_k_groups(self, groups):
         self._check(self.lib.df_set_k_groups(self.h, int(groups)), "df_set_k_groups")
 
+    def df_set_block_precision(self, s_blocks):
+        """Per-aux-block slice counts (sequence of ints 0..8), or None to reset."""
+        if s_blocks is None:
+            self._check(self.lib.df_set_block_precision(self.h, None, 0), "df_set_block_precision")
+            return
+        arr = (ctypes.c_int32 * len(s_blocks))(*[int(v) for v in s_blocks])
+        self._check(self.lib.df_set_block_precision(self.h, arr, len(s_blocks)),
+                    "df_set_block_precision")
+
     def df_get_k_groups(self):
         return self.lib.df_get_k_groups(self.h)
 
@@ -170,6 +185,21 @@ class Context:
                                          C.shape[1], float(occ), _ptr(D), _ptr(J), _ptr(K),
                                          _ptr(energies), _ptr(err_bound)), "df_build_jk")
 
+    def df_prepare_b(self, B, planes, b_exp, b_dig, layout=DF_DENSE):
+        """b_exp [naux*nao] int32, b_dig [planes][naux*nao][ldk] int8 (ldk = nao
+        rounded up to 64); sizes from df_prepare_b_size."""
+        naux, nao = B.shape[0], B.shape[1]
+        self._check(self.lib.df_prepare_b(self.h, _ptr(B), layout, naux, nao, int(planes),
+                                          _ptr(b_exp), _ptr(b_dig)), "df_prepare_b")
+
+    def df_build_jk_sliced(self, b_dig, planes, b_exp, naux, nao, C, occ, D, J, K, energies,
+                           err_bound):
+        """err_bound: 2 doubles (K bound, J bound)."""
+        self._check(self.lib.df_build_jk_sliced(self.h, _ptr(b_dig), int(planes), _ptr(b_exp),
+                                                naux, nao, _ptr(C), C.shape[1], float(occ),
+                                                _ptr(D), _ptr(J), _ptr(K), _ptr(energies),
+                                                _ptr(err_bound)), "df_build_jk_sliced")
+
     def df_metric_cholesky(self, W):
         """In place: the lower triangle of W becomes L (L L^T = W), upper set to 0."""
         self._check(self.lib.df_metric_cholesky(self.h, _ptr(W), W.shape[0]), "df_metric_cholesky")
@@ -203,6 +233,14 @@ class Context:
         self._check(self.lib.df_debug_slice_gemm_i32(self.h, _ptr(a_dig), _ptr(b_dig), m, n, k,
                                                      int(s), _ptr(partials)),
                     "df_debug_slice_gemm_i32")
+
+
+def df_prepare_b_size(naux, nao, planes):
+    n = ctypes.c_size_t()
+    rc = load().df_prepare_b_size(int(naux), int(nao), int(planes), ctypes.byref(n))
+    if rc != DF_OK:
+        raise DFError(rc, "df_prepare_b_size: bad shape or plane count")
+    return n.value
 
 
 # -- adaptive precision rule (host-only C functions; no context needed) -----------

@@ -25,6 +25,10 @@ struct df_ctx {
   std::vector<hipEvent_t> ev;
   int ev_cap = 0;
   int ev_used = 0;
+  // per-aux-block slice counts (empty = the context precision for all blocks)
+  std::vector<int32_t> blk_s;
+  int32_t* blk_dev = nullptr;
+  size_t blk_cap = 0;
 };
 
 namespace {
@@ -45,33 +49,13 @@ int hip_fail(df_ctx* c, hipError_t e, const char* where) {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// Error-bound factor of one emulated product over k terms (slices s >= 1), or
-// the FP64 dot-product factor gamma_k (s == 0):
-//   |Z - Z_hat| <= k 2^(e_r + f_c) kappa.
-// s >= 1: slicing of both operands (2 eps + eps^2, eps the largest dropped
-// tail of a balanced base-256 expansion plus the 62-bit truncation), the digit
-// pairs with a + b >= s + 2 that are not formed (2s + 1 - g pairs of weight
-// 2^(18 - 8g) at each g), and the s - 1 FP64 roundings of the recombination.
-double kappa_of(int s, int64_t k) {
-  const double u = ldexp(1.0, -53);
-  if (s == 0) {
-    const double ku = (double)k * u;
-    return ku / (1.0 - ku);
-  }
-  const double eps = (128.0 / 255.0) * ldexp(1.0, 2 - 8 * s) * (1.0 - ldexp(1.0, -8 * (8 - s))) +
-                     ldexp(1.0, -62);
-  double dropped = 0.0;
-  for (int g = s + 2; g <= 2 * s; ++g) dropped += (double)(2 * s + 1 - g) * ldexp(1.0, 18 - 8 * g);
-  const double rounding = (s - 1) * u * 1.016 * pow(1.0 + u, (double)s);
-  return 2.0 * eps + eps * eps + dropped + rounding;
-}
-
 // Shape-derived sizes shared by the workspace query and the build.
 struct Plan {
   int64_t naux, nao, nocc;
   int pblk, nb, nao_pad, kbp, ncp, kp, groups, jsplit;
+  int naux_pad, jdsplit;
   size_t off_bexp, off_fcol, off_dC, off_X, off_xmax, off_F, off_Xd, off_rho, off_rowdot,
-      off_Jp, off_Kp, off_bsc, off_esc, total;
+      off_Jp, off_Kp, off_bsc, off_esc, off_dD, off_gexp, off_h, off_wd, off_Sj, off_drho, total;
 };
 
 size_t carve(size_t& cur, size_t bytes) {
@@ -96,6 +80,7 @@ Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
   int g = c->k_groups_req;
   if (g <= 0) g = (int)std::min<int64_t>(std::max<int64_t>(1, (1024 + tiles - 1) / tiles), 64);
   p.groups = std::max(1, std::min(g, p.nb));
+  if (!c->blk_s.empty()) p.groups = p.nb;  // per-block precision: one partial per block
   const int64_t nn = nao * nao;
   const int64_t nch = (nn + 511) / 512;
   p.jsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, 2048 / std::max<int64_t>(nch, 1)));
@@ -114,6 +99,22 @@ Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
   p.off_Kp = carve(cur, (size_t)p.groups * nn * 8);
   p.off_bsc = carve(cur, (size_t)p.nb * nao * 3 * 8);
   p.off_esc = carve(cur, (size_t)512 * 8);
+  // sliced mode: D digits, D row exponents, w exponents and digits, J's
+  // integer sums, the per-P bound on rho
+  p.naux_pad = (int)round_up(naux, 64);
+  {
+    const int64_t ngrp = (naux + 3) / 4;
+    int64_t ns = std::max<int64_t>(1, (2048 + nao - 1) / nao);
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, ngrp / 16));
+    ns = std::max<int64_t>(ns, (naux * kMaxSlices + 65535) / 65536);
+    p.jdsplit = (int)std::min<int64_t>(ns, 65535);
+  }
+  p.off_dD = carve(cur, (size_t)kMaxSlices * nao * p.kp);
+  p.off_gexp = carve(cur, (size_t)nao * 4);
+  p.off_h = carve(cur, (size_t)nao * 4);
+  p.off_wd = carve(cur, (size_t)kMaxSlices * nao * p.naux_pad);
+  p.off_Sj = carve(cur, (size_t)kMaxSlices * nn * 8);
+  p.off_drho = carve(cur, (size_t)naux * 8 + 8);
   p.total = cur;
   return p;
 }
@@ -171,10 +172,148 @@ int run_x(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp, const
   int32_t* fcol = at<int32_t>(c, p.off_fcol);
   int8_t* dC = at<int8_t>(c, p.off_dC);
   DF_HIP(launch_col_exp(c->stream, C, p.nao, p.nocc, fcol, c->status), "col_exp");
-  DF_HIP(launch_slice_c(c->stream, C, p.nao, p.nocc, s, fcol, p.ncp, p.kp, dC), "slice_c");
+  DF_HIP(launch_slice_c(c->stream, C, p.nao, p.nocc, s, fcol, p.ncp, p.kp, 0, dC), "slice_c");
   DF_HIP(launch_x_int8(c->stream, s, B, p.naux, (int)p.nao, b_exp, dC, p.ncp, p.kp, fcol,
                        (int)p.nocc, X, 0, xmax, p.pblk, nullptr, nullptr),
          "x_int8");
+  return DF_OK;
+}
+
+// Exponents and digits of X, the blocked K partials, their reduction (stages
+// SLICE_X, K, K_REDUCE) at the context precision; X in the blocked layout.
+int k_stages(df_ctx* c, const Plan& p, const double* X, double occ, double* K, int* fstride) {
+  const int s = c->slices;
+  hipStream_t st = c->stream;
+  const int64_t naux = p.naux, nao = p.nao, nocc = p.nocc;
+  unsigned long long* xmax = at<unsigned long long>(c, p.off_xmax);
+  int32_t* F = at<int32_t>(c, p.off_F);
+  double* Kp = at<double>(c, p.off_Kp);
+  int8_t* Xd = at<int8_t>(c, p.off_Xd);
+  if (s == 0) {
+    DF_HIP(launch_xmax_to_exp(st, xmax, (int64_t)p.nb * nao, F), "xmax_to_exp");
+    *fstride = (int)nao;
+  } else {
+    DF_HIP(launch_slice_x(st, s, X, naux, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp, xmax, F, Xd),
+           "slice_x");
+    *fstride = p.nao_pad;
+  }
+  mark(c, 1 + DF_STAGE_SLICE_X);
+  if (s == 0) {
+    DF_HIP(launch_k_fp64(st, X, naux, (int)nao, (int)nocc, p.pblk, p.nb, p.groups, Kp), "k_fp64");
+  } else {
+    DF_HIP(launch_k_int8(st, s, Xd, F, p.nb, (int)nao, p.nao_pad, p.kbp, p.groups, Kp), "k_int8");
+  }
+  mark(c, 1 + DF_STAGE_K);
+  c->k_groups_used = p.groups;
+  DF_HIP(launch_k_reduce(st, Kp, p.groups, (int)nao, occ, K), "k_reduce");
+  mark(c, 1 + DF_STAGE_K_REDUCE);
+  return DF_OK;
+}
+
+// Error bound of K into err_bound[0].  For s == 0 the FP64 X product is a
+// length-nao dot product and each exchange partial is one accumulation chain
+// of at most naux * nocc terms.
+int k_bound_stage(df_ctx* c, const Plan& p, const int32_t* b_exp, const int32_t* fcol, int fstride,
+                  double occ, double* err_bound) {
+  const int s = c->slices;
+  const int64_t naux = p.naux, nao = p.nao, nocc = p.nocc;
+  const int64_t kb_full = (int64_t)p.pblk * nocc;
+  const int64_t kb_last = (naux - (int64_t)(p.nb - 1) * p.pblk) * nocc;
+  const double k1 = kappa_of(s, nao);
+  const double k2f = s ? kappa_of(s, kb_full) : kappa_of(0, naux * nocc);
+  const double k2l = s ? kappa_of(s, kb_last) : kappa_of(0, naux * nocc);
+  const int32_t* sblk = c->blk_s.empty() ? nullptr : c->blk_dev;
+  DF_HIP(launch_bound(c->stream, b_exp, fcol, (int)nocc, at<int32_t>(c, p.off_F), fstride, naux,
+                      (int)nao, p.pblk, p.nb, k1, k2f, k2l, occ, sblk, at<double>(c, p.off_bsc),
+                      err_bound),
+         "bound");
+  return DF_OK;
+}
+
+// Per-block precision: maximal runs [b0, b1) of consecutive aux blocks that
+// share one slice count.
+struct Run {
+  int b0, b1, s;
+};
+
+std::vector<Run> block_runs(const df_ctx* c) {
+  std::vector<Run> r;
+  const int nb = (int)c->blk_s.size();
+  for (int b = 0; b < nb;) {
+    int e = b + 1;
+    while (e < nb && c->blk_s[e] == c->blk_s[b]) ++e;
+    r.push_back({b, e, c->blk_s[b]});
+    b = e;
+  }
+  return r;
+}
+
+int effective_max_slices(const df_ctx* c) {
+  if (c->blk_s.empty()) return c->slices;
+  int m = 0;
+  for (int v : c->blk_s) m = std::max(m, v);
+  return m;
+}
+
+// X, its digits and the blocked K partials (one per block) with each run of
+// blocks at its own slice count; the X, SLICE_X and K stage marks bracket
+// the X pass and the interleaved slicing and K pass.
+int xk_stages_blocks(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp,
+                     const double* C, const double* D, double* rowdot, double occ, double* K,
+                     int* fstride) {
+  hipStream_t st = c->stream;
+  const int64_t naux = p.naux, nao = p.nao, nocc = p.nocc, nn = nao * nao;
+  double* X = at<double>(c, p.off_X);
+  int32_t* fcol = at<int32_t>(c, p.off_fcol);
+  int8_t* dC = at<int8_t>(c, p.off_dC);
+  unsigned long long* xmax = at<unsigned long long>(c, p.off_xmax);
+  int32_t* F = at<int32_t>(c, p.off_F);
+  double* Kp = at<double>(c, p.off_Kp);
+  int8_t* Xd = at<int8_t>(c, p.off_Xd);
+  const std::vector<Run> runs = block_runs(c);
+  for (const Run& r : runs) {
+    const int64_t P0 = (int64_t)r.b0 * p.pblk;
+    const int64_t P1 = std::min<int64_t>((int64_t)r.b1 * p.pblk, naux);
+    const double* Bp = B + P0 * nn;
+    double* Xr = X + P0 * nao * nocc;  // the blocked layout keeps each block contiguous
+    if (r.s == 0) {
+      DF_HIP(launch_x_fp64(st, Bp, P1 - P0, (int)nao, C, (int)nocc, Xr, 1, xmax + r.b0 * nao,
+                           p.pblk, D, rowdot + P0 * nao),
+             "x_fp64");
+    } else {
+      DF_HIP(launch_x_int8(st, r.s, Bp, P1 - P0, (int)nao, b_exp + P0 * nao, dC, p.ncp, p.kp, fcol,
+                           (int)nocc, Xr, 1, xmax + r.b0 * nao, p.pblk, D, rowdot + P0 * nao),
+             "x_int8");
+    }
+  }
+  mark(c, 1 + DF_STAGE_X);
+  mark(c, 1 + DF_STAGE_SLICE_X);
+  for (const Run& r : runs) {
+    const int64_t P0 = (int64_t)r.b0 * p.pblk;
+    const int64_t P1 = std::min<int64_t>((int64_t)r.b1 * p.pblk, naux);
+    const int nbr = r.b1 - r.b0;
+    const double* Xr = X + P0 * nao * nocc;
+    if (r.s == 0) {
+      for (int b = r.b0; b < r.b1; ++b)
+        DF_HIP(launch_xmax_to_exp(st, xmax + (int64_t)b * nao, nao, F + (int64_t)b * p.nao_pad),
+               "xmax_to_exp");
+      DF_HIP(launch_k_fp64(st, Xr, P1 - P0, (int)nao, (int)nocc, p.pblk, nbr, nbr,
+                           Kp + (int64_t)r.b0 * nn),
+             "k_fp64");
+    } else {
+      DF_HIP(launch_slice_x(st, r.s, Xr, P1 - P0, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp,
+                            xmax + (int64_t)r.b0 * nao, F + (int64_t)r.b0 * p.nao_pad, Xd),
+             "slice_x");
+      DF_HIP(launch_k_int8(st, r.s, Xd, F + (int64_t)r.b0 * p.nao_pad, nbr, (int)nao, p.nao_pad,
+                           p.kbp, nbr, Kp + (int64_t)r.b0 * nn),
+             "k_int8");
+    }
+  }
+  mark(c, 1 + DF_STAGE_K);
+  c->k_groups_used = p.nb;
+  DF_HIP(launch_k_reduce(st, Kp, p.nb, (int)nao, occ, K), "k_reduce");
+  mark(c, 1 + DF_STAGE_K_REDUCE);
+  *fstride = p.nao_pad;
   return DF_OK;
 }
 
@@ -183,7 +322,7 @@ int common_checks(df_ctx* c, const double* B, int layout, int64_t naux, int64_t 
   int rc = check_shape(c, layout, naux, nao, nocc);
   if (rc) return rc;
   if (!B || !C) return fail(c, DF_EINVAL, "null B or C");
-  rc = check_guard(c, c->slices, nao, nocc);
+  rc = check_guard(c, effective_max_slices(c), nao, nocc);
   if (rc) return rc;
   p = make_plan(c, naux, nao, nocc);
   if (!c->ws || c->ws_bytes < p.total) return fail(c, DF_EWORKSPACE, "workspace too small");
@@ -220,6 +359,7 @@ void df_destroy(df_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   (void)hipFree(c->status);
+  if (c->blk_dev) (void)hipFree(c->blk_dev);
   delete c;
 }
 
@@ -243,6 +383,30 @@ int df_set_k_groups(df_ctx* c, int groups) {
   if (!c) return DF_EINVAL;
   if (groups < 0 || groups > 4096) return fail(c, DF_EINVAL, "groups must be 0..4096");
   c->k_groups_req = groups;
+  return DF_OK;
+}
+
+int df_set_block_precision(df_ctx* c, const int32_t* host_s, int64_t nblocks) {
+  if (!c) return DF_EINVAL;
+  if (!host_s) {
+    c->blk_s.clear();
+    return DF_OK;
+  }
+  if (nblocks < 1 || nblocks > (1 << 24)) return fail(c, DF_EINVAL, "nblocks must be 1..2^24");
+  for (int64_t b = 0; b < nblocks; ++b)
+    if (host_s[b] < 0 || host_s[b] > kMaxSlices) return fail(c, DF_EINVAL, "slice counts must be 0..8");
+  if ((size_t)nblocks > c->blk_cap) {
+    if (c->blk_dev) DF_HIP(hipFree(c->blk_dev), "hipFree");
+    c->blk_dev = nullptr;
+    c->blk_cap = 0;
+    DF_HIP(hipMalloc(&c->blk_dev, (size_t)nblocks * sizeof(int32_t)), "hipMalloc");
+    c->blk_cap = (size_t)nblocks;
+  }
+  // the stream may still read the previous counts
+  DF_HIP(hipStreamSynchronize(c->stream), "sync");
+  DF_HIP(hipMemcpy(c->blk_dev, host_s, (size_t)nblocks * sizeof(int32_t), hipMemcpyHostToDevice),
+         "hipMemcpy");
+  c->blk_s.assign(host_s, host_s + nblocks);
   return DF_OK;
 }
 
@@ -309,7 +473,10 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
   if (rc) return rc;
   if (!D || !J || !K || !energies || !err_bound) return fail(c, DF_EINVAL, "null output or D");
   if (!(occ == occ) || isinf(occ)) return fail(c, DF_EINVAL, "occ must be finite");
-  const int s = c->slices;
+  const bool per_block = !c->blk_s.empty();
+  if (per_block && (int64_t)c->blk_s.size() != p.nb)
+    return fail(c, DF_EINVAL, "block precision set for another number of aux blocks");
+  const int s = effective_max_slices(c);
   hipStream_t st = c->stream;
   mark(c, 0);
   if (!b_exp) {
@@ -324,11 +491,15 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
   DF_HIP(launch_fill_u64(st, xmax, (int64_t)p.nb * p.nao, 0ull), "fill xmax");
   DF_HIP(launch_col_exp(st, C, nao, nocc, fcol, c->status), "col_exp");
   int8_t* dC = at<int8_t>(c, p.off_dC);
-  if (s > 0) DF_HIP(launch_slice_c(st, C, nao, nocc, s, fcol, p.ncp, p.kp, dC), "slice_c");
+  if (s > 0) DF_HIP(launch_slice_c(st, C, nao, nocc, s, fcol, p.ncp, p.kp, 0, dC), "slice_c");
   mark(c, 1 + DF_STAGE_PREP);
   // X in the blocked layout, with the B.D row dots of rho fused into the same pass over B
   double* rowdot = at<double>(c, p.off_rowdot);
-  if (s == 0) {
+  int fstride = 0;
+  if (per_block) {
+    rc = xk_stages_blocks(c, p, B, b_exp, C, D, rowdot, occ, K, &fstride);
+    if (rc) return rc;
+  } else if (s == 0) {
     DF_HIP(launch_x_fp64(st, B, naux, (int)nao, C, (int)nocc, X, 1, xmax, p.pblk, D, rowdot),
            "x_fp64");
   } else {
@@ -336,31 +507,11 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
                          xmax, p.pblk, D, rowdot),
            "x_int8");
   }
-  mark(c, 1 + DF_STAGE_X);
-
-  int32_t* F = at<int32_t>(c, p.off_F);
-  double* Kp = at<double>(c, p.off_Kp);
-  int8_t* Xd = at<int8_t>(c, p.off_Xd);
-  int fstride;
-  if (s == 0) {
-    DF_HIP(launch_xmax_to_exp(st, xmax, (int64_t)p.nb * nao, F), "xmax_to_exp");
-    fstride = (int)nao;
-  } else {
-    DF_HIP(launch_slice_x(st, s, X, naux, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp, xmax, F, Xd),
-           "slice_x");
-    fstride = p.nao_pad;
+  if (!per_block) {
+    mark(c, 1 + DF_STAGE_X);
+    rc = k_stages(c, p, X, occ, K, &fstride);
+    if (rc) return rc;
   }
-  mark(c, 1 + DF_STAGE_SLICE_X);
-  if (s == 0) {
-    DF_HIP(launch_k_fp64(st, X, naux, (int)nao, (int)nocc, p.pblk, p.nb, p.groups, Kp), "k_fp64");
-  } else {
-    DF_HIP(launch_k_int8(st, s, Xd, F, p.nb, (int)nao, p.nao_pad, p.kbp, p.groups, Kp), "k_int8");
-  }
-  mark(c, 1 + DF_STAGE_K);
-  c->k_groups_used = p.groups;
-  DF_HIP(launch_k_reduce(st, Kp, p.groups, (int)nao, occ, K), "k_reduce");
-  mark(c, 1 + DF_STAGE_K_REDUCE);
-
   double* rho = at<double>(c, p.off_rho);
   DF_HIP(launch_rho_reduce(st, rowdot, naux, (int)nao, rho), "rho_reduce");
   mark(c, 1 + DF_STAGE_RHO);
@@ -370,17 +521,95 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
          "energies");
   mark(c, 1 + DF_STAGE_ENERGIES);
 
-  // Error bound.  For s == 0 the FP64 X product is a length-nao dot product
-  // and each exchange partial is one accumulation chain of at most
-  // naux * nocc terms.
-  const int64_t kb_full = (int64_t)p.pblk * nocc;
-  const int64_t kb_last = (naux - (int64_t)(p.nb - 1) * p.pblk) * nocc;
-  const double k1 = kappa_of(s, nao);
-  const double k2f = s ? kappa_of(s, kb_full) : kappa_of(0, naux * nocc);
-  const double k2l = s ? kappa_of(s, kb_last) : kappa_of(0, naux * nocc);
-  DF_HIP(launch_bound(st, b_exp, fcol, (int)nocc, F, fstride, naux, (int)nao, p.pblk, p.nb, k1,
-                      k2f, k2l, occ, at<double>(c, p.off_bsc), err_bound),
-         "bound");
+  rc = k_bound_stage(c, p, b_exp, fcol, fstride, occ, err_bound);
+  if (rc) return rc;
+  mark(c, 1 + DF_STAGE_BOUND);
+  if (c->ev_used < c->ev_cap) ++c->ev_used;
+  return DF_OK;
+}
+
+int df_prepare_b_size(int64_t naux, int64_t nao, int planes, size_t* bytes) {
+  if (!bytes || naux < 1 || nao < 1 || nao > 65536 || planes < 1 || planes > kMaxSlices)
+    return DF_EINVAL;
+  *bytes = (size_t)planes * naux * nao * round_up(nao, 64);
+  return DF_OK;
+}
+
+int df_prepare_b(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao, int planes,
+                 int32_t* b_exp, int8_t* b_dig) {
+  const int rc = check_shape(c, layout, naux, nao, 1);
+  if (rc) return rc;
+  if (!B || !b_exp || !b_dig) return fail(c, DF_EINVAL, "null pointer");
+  if (planes < 1 || planes > kMaxSlices) return fail(c, DF_EINVAL, "planes must be 1..8");
+  if (reinterpret_cast<uintptr_t>(b_dig) & 15) return fail(c, DF_EINVAL, "b_dig must be 16-byte aligned");
+  DF_HIP(launch_row_exp(c->stream, B, naux * nao, nao, nao, b_exp, c->status), "row_exp");
+  DF_HIP(launch_slice_planes(c->stream, B, naux * nao, (int)nao, (int)round_up(nao, 64), b_exp,
+                             planes, b_dig),
+         "slice_planes");
+  return DF_OK;
+}
+
+int df_build_jk_sliced(df_ctx* c, const int8_t* b_dig, int planes, const int32_t* b_exp,
+                       int64_t naux, int64_t nao, const double* C, int64_t nocc, double occ,
+                       const double* D, double* J, double* K, double* energies,
+                       double* err_bound) {
+  int rc = check_shape(c, DF_DENSE, naux, nao, nocc);
+  if (rc) return rc;
+  const int s = c->slices;
+  if (!c->blk_s.empty()) return fail(c, DF_EINVAL, "the sliced build uses one slice count: reset block precision");
+  if (planes < 1 || planes > kMaxSlices) return fail(c, DF_EINVAL, "planes must be 1..8");
+  if (s < 1 || s > planes) return fail(c, DF_EINVAL, "the sliced build needs 1 <= slices <= planes");
+  if (!b_dig || !b_exp || !C || !D || !J || !K || !energies || !err_bound)
+    return fail(c, DF_EINVAL, "null pointer");
+  if (reinterpret_cast<uintptr_t>(b_dig) & 15) return fail(c, DF_EINVAL, "b_dig must be 16-byte aligned");
+  if (!(occ == occ) || isinf(occ)) return fail(c, DF_EINVAL, "occ must be finite");
+  rc = check_guard(c, s, nao, nocc);
+  if (rc) return rc;
+  const Plan p = make_plan(c, naux, nao, nocc);
+  if (!c->ws || c->ws_bytes < p.total) return fail(c, DF_EWORKSPACE, "workspace too small");
+  hipStream_t st = c->stream;
+  const int ldk = p.kp;
+  const int64_t bplane = naux * nao * ldk;
+  mark(c, 0);
+  mark(c, 1 + DF_STAGE_BEXP);
+  double* X = at<double>(c, p.off_X);
+  int32_t* fcol = at<int32_t>(c, p.off_fcol);
+  int32_t* g = at<int32_t>(c, p.off_gexp);
+  int8_t* dC = at<int8_t>(c, p.off_dC);
+  int8_t* dD = at<int8_t>(c, p.off_dD);
+  unsigned long long* xmax = at<unsigned long long>(c, p.off_xmax);
+  DF_HIP(launch_fill_u64(st, xmax, (int64_t)p.nb * nao, 0ull), "fill xmax");
+  DF_HIP(launch_col_exp(st, C, nao, nocc, fcol, c->status), "col_exp");
+  DF_HIP(launch_slice_c(st, C, nao, nocc, s, fcol, p.ncp, p.kp, 1, dC), "slice_c");
+  DF_HIP(launch_row_exp(st, D, nao, nao, nao, g, c->status), "row_exp D");
+  DF_HIP(launch_slice_planes(st, D, nao, (int)nao, ldk, g, s, dD), "slice D");
+  mark(c, 1 + DF_STAGE_PREP);
+  double* rowdot = at<double>(c, p.off_rowdot);
+  DF_HIP(launch_x_dig(st, s, b_dig, bplane, naux, (int)nao, ldk, b_exp, dC, p.ncp, fcol, (int)nocc,
+                      X, xmax, p.pblk, dD, g, rowdot),
+         "x_dig");
+  mark(c, 1 + DF_STAGE_X);
+  int fstride = 0;
+  rc = k_stages(c, p, X, occ, K, &fstride);
+  if (rc) return rc;
+  double* rho = at<double>(c, p.off_rho);
+  double* drho = at<double>(c, p.off_drho);
+  const double u = ldexp(1.0, -53);
+  const double kap_sum = (double)(nao - 1) * u * pow(1.0 + u, (double)nao);
+  DF_HIP(launch_rho_seq(st, rowdot, b_exp, g, naux, (int)nao, kappa_of(s, nao), kap_sum, rho, drho),
+         "rho_seq");
+  mark(c, 1 + DF_STAGE_RHO);
+  DF_HIP(launch_j_dig(st, s, b_dig, bplane, ldk, rho, drho, b_exp, naux, (int)nao, p.naux_pad,
+                      p.jdsplit, kappa_of(s, naux), at<int32_t>(c, p.off_h), at<int8_t>(c, p.off_wd),
+                      at<unsigned long long>(c, p.off_Sj),
+                      reinterpret_cast<unsigned long long*>(err_bound + 1), J),
+         "j_dig");
+  mark(c, 1 + DF_STAGE_J);
+  DF_HIP(launch_energies(st, rho, naux, D, K, (int)nao, at<double>(c, p.off_esc), energies),
+         "energies");
+  mark(c, 1 + DF_STAGE_ENERGIES);
+  rc = k_bound_stage(c, p, b_exp, fcol, fstride, occ, err_bound);
+  if (rc) return rc;
   mark(c, 1 + DF_STAGE_BOUND);
   if (c->ev_used < c->ev_cap) ++c->ev_used;
   return DF_OK;

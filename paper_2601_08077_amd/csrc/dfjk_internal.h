@@ -45,6 +45,27 @@ __device__ __forceinline__ uint32_t digit_byte(uint64_t w, int k) {
   return (uint32_t)(w >> (8 * (8 - k))) & 0xffu;
 }
 
+// Error-bound factor of one emulated product over k terms (slices s >= 1), or
+// the FP64 dot-product factor gamma_k (s == 0):
+//   |Z - Z_hat| <= k 2^(e_r + f_c) kappa.
+// s >= 1: slicing of both operands (2 eps + eps^2, eps the largest dropped
+// tail of a balanced base-256 expansion plus the 62-bit truncation), the digit
+// pairs with a + b >= s + 2 that are not formed (2s + 1 - g pairs of weight
+// 2^(18 - 8g) at each g), and the s - 1 FP64 roundings of the recombination.
+__host__ __device__ inline double kappa_of(int s, int64_t k) {
+  const double u = 0x1p-53;
+  if (s == 0) {
+    const double ku = (double)k * u;
+    return ku / (1.0 - ku);
+  }
+  const double eps = (128.0 / 255.0) * ldexp(1.0, 2 - 8 * s) * (1.0 - ldexp(1.0, -8 * (8 - s))) +
+                     0x1p-62;
+  double dropped = 0.0;
+  for (int g = s + 2; g <= 2 * s; ++g) dropped += (double)(2 * s + 1 - g) * ldexp(1.0, 18 - 8 * g);
+  const double rounding = (s - 1) * u * 1.016 * pow(1.0 + u, (double)s);
+  return 2.0 * eps + eps * eps + dropped + rounding;
+}
+
 __device__ __forceinline__ double abs_max_bits_to_double(unsigned long long b) {
   return __longlong_as_double((long long)b);
 }
@@ -64,9 +85,9 @@ hipError_t launch_col_exp(hipStream_t st, const double* C, int64_t nao, int64_t 
 hipError_t launch_slice_rows(hipStream_t st, const double* A, int64_t rows, int64_t cols,
                              int64_t lda, int s, const int32_t* e, int8_t* digits);
 // C digits in the operand layout of the INT8 X product: [s][ncp][kp], k in the
-// slot order of the B-tile loader, zero padded.
+// slot order of the B-tile loader (natural = 0) or in natural order, zero padded.
 hipError_t launch_slice_c(hipStream_t st, const double* C, int64_t nao, int64_t nocc, int s,
-                          const int32_t* f, int ncp, int kp, int8_t* dC);
+                          const int32_t* f, int ncp, int kp, int natural, int8_t* dC);
 hipError_t launch_fill_u64(hipStream_t st, unsigned long long* p, int64_t n,
                            unsigned long long v);
 hipError_t launch_fill_i32(hipStream_t st, int* p, int64_t n, int v);
@@ -119,11 +140,32 @@ hipError_t launch_k_reduce(hipStream_t st, const double* Kp, int groups, int nao
 // scratch: 2 * 256 doubles.
 hipError_t launch_energies(hipStream_t st, const double* rho, int64_t naux, const double* D,
                            const double* K, int nao, double* scratch, double* energies);
-// Error bound of the blocked K; kappa1 / kappa2 per block supplied by the host.
+// Error bound of the blocked K: kappa1 / kappa2 from the host, or, with sblk
+// (device [nb] slice counts) given, each block's own factors.
 hipError_t launch_bound(hipStream_t st, const int32_t* b_exp, const int32_t* f_col, int nocc,
                         const int32_t* F, int fstride, int64_t naux, int nao, int pblk, int nb,
                         double kappa1, double kappa2_full, double kappa2_last, double occ,
-                        double* scratch,
-                        double* err_bound);
+                        const int32_t* sblk, double* scratch, double* err_bound);
+
+
+// sliced.hip: the mode with B held as digit planes [planes][naux*nao][ldk]
+// (ldk = nao rounded up to 64, zero padded).
+hipError_t launch_slice_planes(hipStream_t st, const double* A, int64_t rows, int cols, int ldk,
+                               const int32_t* e, int planes, int8_t* dig);
+// X (blocked layout) from the B planes and the natural-order C digits; with
+// Dd / d_exp, rowdot[P*nao + mu] = the emulated B row . D row.
+hipError_t launch_x_dig(hipStream_t st, int s, const int8_t* Bd, int64_t bplane, int64_t naux,
+                        int nao, int ldk, const int32_t* b_exp, const int8_t* dC, int ncp,
+                        const int32_t* f_col, int nocc, double* X, unsigned long long* xmax,
+                        int pblk, const int8_t* Dd, const int32_t* d_exp, double* rowdot);
+// rho (mu ascending) and its per-P error bound.
+hipError_t launch_rho_seq(hipStream_t st, const double* rowdot, const int32_t* b_exp,
+                          const int32_t* d_exp, int64_t naux, int nao, double kap_row,
+                          double kap_sum, double* rho, double* drho);
+// J from the B planes; jbound receives the Coulomb error bound (as double bits).
+hipError_t launch_j_dig(hipStream_t st, int s, const int8_t* Bd, int64_t bplane, int ldk,
+                        const double* rho, const double* drho, const int32_t* b_exp, int64_t naux,
+                        int nao, int naux_pad, int nsplit, double kap_j, int32_t* h, int8_t* wd,
+                        unsigned long long* Sj, unsigned long long* jbound, double* J);
 
 }  // namespace dfjk

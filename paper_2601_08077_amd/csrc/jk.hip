@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_rho_reduce(const double* __restrict__ r
 __global__ void k_bound_prep(const int32_t* __restrict__ b_exp, const int32_t* __restrict__ f_col,
                              int nocc, const int32_t* __restrict__ F, int fstride, int64_t naux,
                              int nao, int pblk, int nb, double kappa1,
-                             double* __restrict__ scratch) {
+                             const int32_t* __restrict__ sblk, double* __restrict__ scratch) {
   double fsum = 0.0, fmx = 0.0;
   for (int i = 0; i < nocc; ++i) {
     const double v = ldexp(1.0, f_col[i]);
@@ -165,14 +165,15 @@ __global__ void k_bound_prep(const int32_t* __restrict__ b_exp, const int32_t* _
     const int b = (int)(idx / nao), mu = (int)(idx - (int64_t)b * nao);
     const int64_t p0 = (int64_t)b * pblk;
     const int64_t p1 = p0 + pblk < naux ? p0 + pblk : naux;
+    const double k1 = sblk ? kappa_of(sblk[b], nao) : kappa1;
     double se = 0.0, me = 0.0;
     for (int64_t P = p0; P < p1; ++P) {
       const double v = ldexp(1.0, b_exp[P * nao + mu]);
       se += v;
       me = fmax(me, v);
     }
-    scratch[3 * idx + 0] = nao * kappa1 * fsum * se;
-    scratch[3 * idx + 1] = nao * kappa1 * fmx * me;
+    scratch[3 * idx + 0] = nao * k1 * fsum * se;
+    scratch[3 * idx + 1] = nao * k1 * fmx * me;
     scratch[3 * idx + 2] = ldexp(1.0, F[(int64_t)b * fstride + mu]);
   }
 }
@@ -183,7 +184,8 @@ __global__ void k_bound_prep(const int32_t* __restrict__ b_exp, const int32_t* _
 __global__ __launch_bounds__(256) void k_bound(const double* __restrict__ scratch, int nao, int nb,
                                                int64_t naux, int pblk, int nocc,
                                                double kappa2_full, double kappa2_last, double occ,
-                                               int occ_pow2, double* __restrict__ err_bound) {
+                                               int occ_pow2, const int32_t* __restrict__ sblk,
+                                               double* __restrict__ err_bound) {
   const double u = 0x1p-53;
   const double accf = (nb - 1) * u * pow(1.0 + u, (double)nb);
   double best = 0.0;
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(256) void k_bound(const double* __restrict__ scratc
       const int64_t p0 = (int64_t)b * pblk;
       const int64_t kb = ((p0 + pblk < naux ? p0 + pblk : naux) - p0) * nocc;
       const double pp = sm[2] * sn[2];
-      const double k2 = b == nb - 1 ? kappa2_last : kappa2_full;
+      const double k2 = sblk ? kappa_of(sblk[b], kb) : (b == nb - 1 ? kappa2_last : kappa2_full);
       sum += sm[0] * sn[2] + (sm[2] + sm[1]) * sn[0] + (double)kb * pp * k2;
       kabs += (double)kb * pp * (1.0 + k2);
     }
@@ -268,13 +270,12 @@ hipError_t launch_rho_reduce(hipStream_t st, const double* rowdot, int64_t naux,
 hipError_t launch_bound(hipStream_t st, const int32_t* b_exp, const int32_t* f_col, int nocc,
                         const int32_t* F, int fstride, int64_t naux, int nao, int pblk, int nb,
                         double kappa1, double kappa2_full, double kappa2_last, double occ,
-                        double* scratch,
-                        double* err_bound) {
+                        const int32_t* sblk, double* scratch, double* err_bound) {
   const int64_t n = (int64_t)nb * nao;
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_bound_prep, dim3((unsigned)g), dim3(256), 0, st, b_exp, f_col, nocc, F,
-                     fstride, naux, nao, pblk, nb, kappa1, scratch);
+                     fstride, naux, nao, pblk, nb, kappa1, sblk, scratch);
   hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(1), 0, st, err_bound);
   int occ_pow2 = 0;
   {
@@ -286,7 +287,7 @@ hipError_t launch_bound(hipStream_t st, const int32_t* b_exp, const int32_t* f_c
   int64_t g2 = (nn + 255) / 256;
   if (g2 > 2048) g2 = 2048;
   hipLaunchKernelGGL(k_bound, dim3((unsigned)g2), dim3(256), 0, st, scratch, nao, nb, naux, pblk,
-                     nocc, kappa2_full, kappa2_last, occ, occ_pow2, err_bound);
+                     nocc, kappa2_full, kappa2_last, occ, occ_pow2, sblk, err_bound);
   return hipGetLastError();
 }
 

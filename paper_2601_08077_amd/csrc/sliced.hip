@@ -1,0 +1,489 @@
+// Sliced mode of the build: B is kept as INT8 digit planes (sliced once per B;
+// any prefix of the planes serves every level), and X, rho and J are all formed
+// from those digits; FP64 remains in the recombinations and the energies.
+//   X   = B C               (Eq. 5): INT8 MFMA, A fragments read from the planes
+//   rho = sum_{mu,nu} B D   (Eq. 3): per row (P, mu), an INT8 dot (v_dot4) of the
+//                                  row's digits with the digits of D's row mu on
+//                                  the same fragments, recombined in FP64, then
+//                                  summed over mu in ascending order
+//   J   = sum_P rho_P B_P   (Eq. 4): w[P, mu] = rho_P 2^e[P, mu] sliced over P for
+//                                  each mu; INT8 dots with the B digits over P
+//                                  (lower triangle), mirrored
+// Digit planes share one row stride `ldk` (the row length rounded up to 64
+// bytes, zero padded), so every 16-byte fragment load stays inside its row.
+#include "dfjk_internal.h"
+
+namespace dfjk {
+namespace {
+
+__device__ __forceinline__ uint32_t pack4(uint64_t w0, uint64_t w1, uint64_t w2, uint64_t w3,
+                                          int k) {
+  return digit_byte(w0, k) | (digit_byte(w1, k) << 8) | (digit_byte(w2, k) << 16) |
+         (digit_byte(w3, k) << 24);
+}
+
+// dig[a][r][ldk] = digit a + 1 of A[r][c] (row exponent e[r]); columns c >= cols
+// are zero.  One thread per 16 output bytes of a row.
+__global__ __launch_bounds__(256) void k_slice_planes(const double* __restrict__ A, int64_t rows,
+                                                      int cols, int ldk,
+                                                      const int32_t* __restrict__ e, int planes,
+                                                      int8_t* __restrict__ dig) {
+  const int nc = ldk / 16;
+  const int64_t total = rows * nc;
+  const int64_t plane = rows * (int64_t)ldk;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / nc;
+    const int c0 = (int)(idx - r * nc) * 16;
+    const double* src = A + r * cols + c0;
+    const int er = e[r];
+    uint64_t wd[16];
+    if (c0 + 16 <= cols && (cols & 1) == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double2 p = *reinterpret_cast<const double2*>(src + 2 * j);
+        wd[2 * j] = digit_word(p.x, er);
+        wd[2 * j + 1] = digit_word(p.y, er);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) wd[j] = c0 + j < cols ? digit_word(src[j], er) : 0ull;
+    }
+    int8_t* dst = dig + r * ldk + c0;
+    for (int a = 0; a < planes; ++a) {
+      i32x4 pk;
+      pk[0] = (int)pack4(wd[0], wd[1], wd[2], wd[3], a + 1);
+      pk[1] = (int)pack4(wd[4], wd[5], wd[6], wd[7], a + 1);
+      pk[2] = (int)pack4(wd[8], wd[9], wd[10], wd[11], a + 1);
+      pk[3] = (int)pack4(wd[12], wd[13], wd[14], wd[15], a + 1);
+      *reinterpret_cast<i32x4*>(dst + a * plane) = pk;
+    }
+  }
+}
+
+// X = B C from the B digit planes.  Tile: 64 rows x 16 NF columns; wave w owns
+// rows 16 (w & 3) .. +15 and column fragments [NFW (w >> 2), +NFW) (NH column
+// halves, NF = NH NFW).  Lane (q, r) holds the 16 bytes k0 + 16 q .. +15 of its
+// row in every plane (the same k order as the C digits in LDS, natural k), so
+// the MFMA sums over the 64 k of a chunk.  With D digits given, waves of half
+// 0 also accumulate the row dots of rho per anti-diagonal with v_dot4 on the
+// same fragments (exact int32), then recombine them in FP64.
+template <int S, int NFW, int NH>
+__global__ __launch_bounds__(256 * NH) void k_x_dig(
+    const int8_t* __restrict__ Bd, int64_t bplane, int64_t M, int ldk,
+    const int32_t* __restrict__ b_exp, const int8_t* __restrict__ dC, int ncp,
+    const int32_t* __restrict__ f_col, int nocc, double* __restrict__ X,
+    unsigned long long* __restrict__ xmax, int nao, int pblk,
+    const int8_t* __restrict__ Dd, const int32_t* __restrict__ d_exp, double* __restrict__ rowdot) {
+  constexpr int NF = NFW * NH, NT = 16 * NF, ROW = 80, NTHR = 256 * NH;
+  constexpr int CUNITS = S * NT * 4;
+  constexpr int CPER = (CUNITS + NTHR - 1) / NTHR;
+  __shared__ __attribute__((aligned(16))) int8_t Cs[S][NT][ROW];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
+  const int wr = w & 3, half = w >> 2;
+  int64_t m0 = (int64_t)blockIdx.x * 64;
+  if (nao % 64 == 0) {  // workgroups running together share the rows of D
+    const int64_t naux = M / nao;
+    const int64_t mt = blockIdx.x / naux, P = blockIdx.x - mt * naux;
+    m0 = P * nao + mt * 64;
+  }
+  const int n0 = blockIdx.y * NT;
+  const int64_t arow = m0 + wr * 16 + r16;
+  const bool aok = arow < M;
+  const int8_t* asrc = Bd + (aok ? arow : 0) * (int64_t)ldk + q * 16;
+  const bool want_rd = Dd != nullptr && blockIdx.y == 0 && half == 0;
+  const int mu_a = aok ? (int)(arow % nao) : 0;
+  const int8_t* dsrc = (Dd ? Dd : Bd) + (int64_t)mu_a * ldk + q * 16;
+  const int64_t dplane = (int64_t)nao * ldk;
+  const int nch = ldk / 64;
+
+  const int8_t* csrc[CPER];
+  int cdst[CPER];
+#pragma unroll
+  for (int i = 0; i < CPER; ++i) {
+    const int u = t + NTHR * i;
+    const int uu = u < CUNITS ? u : 0;
+    const int a = uu / (NT * 4), rem = uu - a * (NT * 4), col = rem >> 2, part = rem & 3;
+    csrc[i] = dC + ((int64_t)a * ncp + n0 + col) * ldk + part * 16;
+    cdst[i] = (a * NT + col) * ROW + part * 16;
+  }
+
+  i32x4 acc[S][NFW];
+#pragma unroll
+  for (int g = 0; g < S; ++g)
+#pragma unroll
+    for (int f = 0; f < NFW; ++f) acc[g][f] = i32x4{0, 0, 0, 0};
+  int rdi[S];
+#pragma unroll
+  for (int g = 0; g < S; ++g) rdi[g] = 0;
+
+  i32x4 af[S], cpre[CPER];
+#define DFJK_XD_LOAD(CC)                                                                 \
+  {                                                                                      \
+    const int kb = (CC) * 64;                                                            \
+    _Pragma("unroll") for (int a = 0; a < S; ++a) af[a] =                                \
+        *reinterpret_cast<const i32x4*>(asrc + a * bplane + kb);                         \
+    _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                   \
+      if (t + NTHR * i < CUNITS) cpre[i] = *reinterpret_cast<const i32x4*>(csrc[i] + kb); \
+    }                                                                                    \
+  }
+  DFJK_XD_LOAD(0)
+  for (int c = 0; c < nch; ++c) {
+    const int k0 = c * 64;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < CPER; ++i)
+      if (t + NTHR * i < CUNITS) *reinterpret_cast<i32x4*>(&Cs[0][0][0] + cdst[i]) = cpre[i];
+    __syncthreads();
+    i32x4 acur[S];
+#pragma unroll
+    for (int a = 0; a < S; ++a) acur[a] = af[a];
+    if (c + 1 < nch) DFJK_XD_LOAD(c + 1)
+    if (want_rd) {
+      i32x4 dd[S];
+#pragma unroll
+      for (int b = 0; b < S; ++b) dd[b] = *reinterpret_cast<const i32x4*>(dsrc + b * dplane + k0);
+#pragma unroll
+      for (int a = 0; a < S; ++a)
+#pragma unroll
+        for (int b = 0; b < S - a; ++b) {
+          int v = rdi[a + b];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v = __builtin_amdgcn_sdot4(acur[a][j], dd[b][j], v, false);
+          rdi[a + b] = v;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < NFW; ++f) {
+      i32x4 bf[S];
+#pragma unroll
+      for (int b = 0; b < S; ++b)
+        bf[b] = *reinterpret_cast<const i32x4*>(&Cs[b][(half * NFW + f) * 16 + r16][q * 16]);
+#pragma unroll
+      for (int a = 0; a < S; ++a)
+#pragma unroll
+        for (int b = 0; b < S - a; ++b)
+          acc[a + b][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(acur[a], bf[b], acc[a + b][f], 0, 0, 0);
+    }
+  }
+#undef DFJK_XD_LOAD
+
+  if (want_rd) {
+    // exact sums over the four lane groups of the row, then its recombination
+#pragma unroll
+    for (int g = 0; g < S; ++g) {
+      rdi[g] += __shfl_xor(rdi[g], 16);
+      rdi[g] += __shfl_xor(rdi[g], 32);
+    }
+    if (q == 0 && aok) {
+      const int base = b_exp[arow] + d_exp[mu_a] + 4;
+      double z = 0.0;
+#pragma unroll
+      for (int g = S + 1; g >= 2; --g) z += ldexp((double)rdi[g - 2], base - 8 * g);
+      rowdot[arow] = z;
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = m0 + wr * 16 + q * 4 + r;
+    const bool vr = row < M;
+    const int er = vr ? b_exp[row] : 0;
+    const int64_t P = vr ? row / nao : 0;
+    const int mu = (int)(row - P * nao);
+    const int64_t b = P / pblk;
+    double* xrow = X + (((b * nao + mu) * pblk + (P - b * pblk)) * (int64_t)nocc);
+    double rmax = 0.0;
+#pragma unroll
+    for (int f = 0; f < NFW; ++f) {
+      const int col = n0 + (half * NFW + f) * 16 + r16;
+      if (vr && col < nocc) {
+        const int base = er + f_col[col] + 4;
+        double z = 0.0;
+#pragma unroll
+        for (int g = S + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][f][r], base - 8 * g);
+        xrow[col] = z;
+        rmax = fmax(rmax, fabs(z));
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
+    if (r16 == 0 && vr)
+      atomicMax(&xmax[b * nao + mu], (unsigned long long)__double_as_longlong(rmax));
+  }
+}
+
+// rho_P = sum_mu rowdot[P nao + mu] with mu ascending (one thread per P), and
+// the bound on |rho_P - rho_hat_P|: the emulated row dots (nao terms each,
+// exponents e_B + g) plus the nao - 1 roundings of the mu sum.
+__global__ void k_rho_seq(const double* __restrict__ rowdot, const int32_t* __restrict__ b_exp,
+                          const int32_t* __restrict__ d_exp, int64_t naux, int nao,
+                          double kap_row, double kap_sum, double* __restrict__ rho,
+                          double* __restrict__ drho) {
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= naux) return;
+  const double* r = rowdot + P * nao;
+  const int32_t* e = b_exp + P * nao;
+  double a = 0.0, sabs = 0.0, srow = 0.0;
+  for (int mu = 0; mu < nao; ++mu) {
+    const double v = r[mu];
+    a += v;
+    sabs += fabs(v);
+    srow += ldexp(1.0, e[mu] + d_exp[mu]);
+  }
+  rho[P] = a;
+  drho[P] = (double)nao * kap_row * srow + kap_sum * sabs;
+}
+
+// For one mu: w[P] = rho_P 2^e[P, mu]; h_mu = exponent of max_P |w|; the digit
+// planes wd[a][mu][P] (P padded to naux_pad with zeros); and the Coulomb error
+// bound at mu, naux 2^h kappa(naux) + sum_P drho_P 2^e[P, mu], max-ed into
+// jbound (non-negative doubles compare as their bit patterns).
+__global__ __launch_bounds__(256) void k_slice_w(const double* __restrict__ rho,
+                                                 const double* __restrict__ drho,
+                                                 const int32_t* __restrict__ b_exp, int64_t naux,
+                                                 int nao, int S, int naux_pad, double kap_j,
+                                                 int32_t* __restrict__ h, int8_t* __restrict__ wd,
+                                                 unsigned long long* __restrict__ jbound) {
+  __shared__ double red[2][4];
+  const int mu = blockIdx.x, t = threadIdx.x;
+  double m = 0.0, prop = 0.0;
+  for (int64_t P = t; P < naux; P += 256) {
+    const int e = b_exp[P * nao + mu];
+    m = fmax(m, fabs(ldexp(rho[P], e)));
+    prop += drho[P] * ldexp(1.0, e);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    m = fmax(m, __shfl_xor(m, off));
+    prop += __shfl_xor(prop, off);
+  }
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = m;
+    red[1][t >> 6] = prop;
+  }
+  __syncthreads();
+  m = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+  const int e = exp_of_max(m);
+  if (t == 0) {
+    h[mu] = e;
+    const double pr = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    const double bnd = (double)naux * ldexp(1.0, e) * kap_j + pr;
+    atomicMax(jbound, (unsigned long long)__double_as_longlong(bnd));
+  }
+  const int64_t plane = (int64_t)nao * naux_pad;
+  int8_t* dst = wd + (int64_t)mu * naux_pad;
+  for (int64_t P = t; P < naux_pad; P += 256) {
+    uint64_t wv = 0;
+    if (P < naux) wv = digit_word(ldexp(rho[P], b_exp[P * nao + mu]), e);
+    for (int a = 0; a < S; ++a) dst[a * plane + P] = (int8_t)digit_byte(wv, a + 1);
+  }
+}
+
+// 4 x 4 byte transpose: byte p of t[c] = byte c of v[p].
+__device__ __forceinline__ void transpose4(uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
+                                           uint32_t& t0, uint32_t& t1, uint32_t& t2,
+                                           uint32_t& t3) {
+  // __builtin_amdgcn_perm(hi, lo, sel): byte i of the result is byte sel_i of
+  // the 64-bit value (hi << 32) | lo.
+  const uint32_t lo01 = __builtin_amdgcn_perm(v1, v0, 0x05010400u);  // v0b0 v1b0 v0b1 v1b1
+  const uint32_t hi01 = __builtin_amdgcn_perm(v1, v0, 0x07030602u);  // v0b2 v1b2 v0b3 v1b3
+  const uint32_t lo23 = __builtin_amdgcn_perm(v3, v2, 0x05010400u);
+  const uint32_t hi23 = __builtin_amdgcn_perm(v3, v2, 0x07030602u);
+  t0 = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+  t1 = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+  t2 = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+  t3 = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+}
+
+// Integer sums of J over one split of the aux range, for row mu and nu <= mu:
+//   Sj[g][mu][nu] += sum_P sum_{a+b=g} wd[a][mu][P] Bd[b][P, mu][nu]  (int64 atomics)
+// Thread (pl, c) owns the 16 nu of chunk c and the groups of 4 consecutive P
+// congruent to pl; the four B rows of a group are transposed in registers so
+// that v_dot4 runs over P; partial sums are combined over pl in LDS.
+template <int S>
+__global__ __launch_bounds__(256) void k_j_dig(const int8_t* __restrict__ Bd, int64_t bplane,
+                                               int ldk, const int8_t* __restrict__ wd,
+                                               int naux_pad, int64_t naux, int nao, int nsplit,
+                                               unsigned long long* __restrict__ Sj) {
+  __shared__ int red[256 * 17];
+  const int mu = blockIdx.x, split = blockIdx.y, t = threadIdx.x;
+  const int64_t ngrp = (naux + 3) / 4;
+  const int64_t g_lo = split * ngrp / nsplit, g_hi = (split + 1) * ngrp / nsplit;
+  const int nch = mu / 16 + 1;
+  const int64_t wplane = (int64_t)nao * naux_pad;
+  const int8_t* wrow = wd + (int64_t)mu * naux_pad;
+  const int64_t nn = (int64_t)nao * nao;
+  const int64_t prow = (int64_t)nao * ldk;
+  for (int cbase = 0; cbase < nch; cbase += 256) {
+    const int ncur = min(256, nch - cbase);
+    const int npl = 256 / ncur;
+    const int pl = t / ncur, c = cbase + (t - pl * ncur);
+    int acc[S][16];
+#pragma unroll
+    for (int g = 0; g < S; ++g)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[g][j] = 0;
+    if (pl < npl) {
+      const int8_t* bbase = Bd + (int64_t)mu * ldk + c * 16;
+      for (int64_t G = g_lo + pl; G < g_hi; G += npl) {
+        const int64_t P0 = 4 * G;
+        int wv[S];
+#pragma unroll
+        for (int a = 0; a < S; ++a) wv[a] = *reinterpret_cast<const int*>(wrow + a * wplane + P0);
+#pragma unroll
+        for (int b = 0; b < S; ++b) {
+          i32x4 v[4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+            v[p] = P0 + p < naux
+                       ? *reinterpret_cast<const i32x4*>(bbase + b * bplane + (P0 + p) * prow)
+                       : i32x4{0, 0, 0, 0};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            uint32_t tt[4];
+            transpose4((uint32_t)v[0][j], (uint32_t)v[1][j], (uint32_t)v[2][j], (uint32_t)v[3][j],
+                       tt[0], tt[1], tt[2], tt[3]);
+#pragma unroll
+            for (int a = 0; a < S - b; ++a)
+#pragma unroll
+              for (int cc = 0; cc < 4; ++cc)
+                acc[a + b][4 * j + cc] =
+                    __builtin_amdgcn_sdot4(wv[a], (int)tt[cc], acc[a + b][4 * j + cc], false);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < S; ++g) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 16; ++j) red[t * 17 + j] = acc[g][j];
+      __syncthreads();
+      for (int item = t; item < ncur * 16; item += 256) {
+        const int cc = item >> 4, j = item & 15;
+        int sum = 0;
+        for (int p = 0; p < npl; ++p) sum += red[(p * ncur + cc) * 17 + j];
+        const int nu = (cbase + cc) * 16 + j;
+        if (nu <= mu)
+          atomicAdd(&Sj[g * nn + (int64_t)mu * nao + nu], (unsigned long long)(long long)sum);
+      }
+    }
+  }
+}
+
+// J[mu][nu] = J[nu][mu] = sum_{g = s+1 .. 2} ldexp(Sj[g], h_mu + 4 - 8 g), nu <= mu.
+__global__ void k_j_recombine(const unsigned long long* __restrict__ Sj, int S, int nao,
+                              const int32_t* __restrict__ h, double* __restrict__ J) {
+  const int64_t nn = (int64_t)nao * nao;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int mu = (int)(e / nao), nu = (int)(e - (int64_t)mu * nao);
+    if (nu > mu) continue;
+    double z = 0.0;
+    for (int g = S + 1; g >= 2; --g)
+      z += ldexp((double)(long long)Sj[(int64_t)(g - 2) * nn + e], h[mu] + 4 - 8 * g);
+    J[e] = z;
+    J[(int64_t)nu * nao + mu] = z;
+  }
+}
+
+inline unsigned cap(int64_t n, int64_t c = 65536) {
+  int64_t g = (n + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : (g > c ? c : g));
+}
+
+template <int S>
+hipError_t x_dig_s(hipStream_t st, const int8_t* Bd, int64_t bplane, int64_t M, int ldk,
+                   const int32_t* b_exp, const int8_t* dC, int ncp, const int32_t* f_col,
+                   int nocc, double* X, unsigned long long* xmax, int nao, int pblk,
+                   const int8_t* Dd, const int32_t* d_exp, double* rowdot) {
+  const unsigned gx = (unsigned)((M + 63) / 64);
+#define DFJK_XD(NFW, NH)                                                                      \
+  hipLaunchKernelGGL((k_x_dig<S, NFW, NH>), dim3(gx, ncp / (16 * NFW * NH)), dim3(256 * NH), 0, \
+                     st, Bd, bplane, M, ldk, b_exp, dC, ncp, f_col, nocc, X, xmax, nao, pblk, Dd, \
+                     d_exp, rowdot)
+  if (ncp % 96 == 0) {
+    if (S <= 2) DFJK_XD(6, 1);
+    else DFJK_XD(3, 2);
+  } else if (ncp % 64 == 0) {
+    if (S <= 3) DFJK_XD(4, 1);
+    else DFJK_XD(2, 2);
+  } else {
+    DFJK_XD(1, 2);
+  }
+#undef DFJK_XD
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_slice_planes(hipStream_t st, const double* A, int64_t rows, int cols, int ldk,
+                               const int32_t* e, int planes, int8_t* dig) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slice_planes, dim3(cap(rows * (ldk / 16))), dim3(256), 0, st, A, rows, cols,
+                     ldk, e, planes, dig);
+  return hipGetLastError();
+}
+
+hipError_t launch_x_dig(hipStream_t st, int s, const int8_t* Bd, int64_t bplane, int64_t naux,
+                        int nao, int ldk, const int32_t* b_exp, const int8_t* dC, int ncp,
+                        const int32_t* f_col, int nocc, double* X, unsigned long long* xmax,
+                        int pblk, const int8_t* Dd, const int32_t* d_exp, double* rowdot) {
+  const int64_t M = naux * nao;
+#define DFJK_XDS(SS) \
+  return x_dig_s<SS>(st, Bd, bplane, M, ldk, b_exp, dC, ncp, f_col, nocc, X, xmax, nao, pblk, Dd, d_exp, rowdot)
+  switch (s) {
+    case 1: DFJK_XDS(1);
+    case 2: DFJK_XDS(2);
+    case 3: DFJK_XDS(3);
+    case 4: DFJK_XDS(4);
+    case 5: DFJK_XDS(5);
+    case 6: DFJK_XDS(6);
+    case 7: DFJK_XDS(7);
+    case 8: DFJK_XDS(8);
+    default: return hipErrorInvalidValue;
+  }
+#undef DFJK_XDS
+}
+
+hipError_t launch_rho_seq(hipStream_t st, const double* rowdot, const int32_t* b_exp,
+                          const int32_t* d_exp, int64_t naux, int nao, double kap_row,
+                          double kap_sum, double* rho, double* drho) {
+  hipLaunchKernelGGL(k_rho_seq, dim3((unsigned)((naux + 255) / 256)), dim3(256), 0, st, rowdot,
+                     b_exp, d_exp, naux, nao, kap_row, kap_sum, rho, drho);
+  return hipGetLastError();
+}
+
+hipError_t launch_j_dig(hipStream_t st, int s, const int8_t* Bd, int64_t bplane, int ldk,
+                        const double* rho, const double* drho, const int32_t* b_exp, int64_t naux,
+                        int nao, int naux_pad, int nsplit, double kap_j, int32_t* h, int8_t* wd,
+                        unsigned long long* Sj, unsigned long long* jbound, double* J) {
+  const int64_t nn = (int64_t)nao * nao;
+  hipError_t e = launch_fill_u64(st, Sj, (int64_t)s * nn, 0ull);
+  if (e != hipSuccess) return e;
+  e = launch_fill_u64(st, jbound, 1, 0ull);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_slice_w, dim3((unsigned)nao), dim3(256), 0, st, rho, drho, b_exp, naux, nao,
+                     s, naux_pad, kap_j, h, wd, jbound);
+  const dim3 grid((unsigned)nao, (unsigned)nsplit);
+#define DFJK_JD(SS)                                                                            \
+  hipLaunchKernelGGL((k_j_dig<SS>), grid, dim3(256), 0, st, Bd, bplane, ldk, wd, naux_pad, naux, \
+                     nao, nsplit, Sj)
+  switch (s) {
+    case 1: DFJK_JD(1); break;
+    case 2: DFJK_JD(2); break;
+    case 3: DFJK_JD(3); break;
+    case 4: DFJK_JD(4); break;
+    case 5: DFJK_JD(5); break;
+    case 6: DFJK_JD(6); break;
+    case 7: DFJK_JD(7); break;
+    case 8: DFJK_JD(8); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef DFJK_JD
+  hipLaunchKernelGGL(k_j_recombine, dim3(cap(nn, 4096)), dim3(256), 0, st, Sj, s, nao, h, J);
+  return hipGetLastError();
+}
+
+}  // namespace dfjk

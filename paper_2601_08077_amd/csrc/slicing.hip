@@ -64,9 +64,10 @@ __global__ void k_slice_rows(const double* __restrict__ A, int64_t rows, int64_t
 
 // Digit planes of C^T in the right-operand layout of the INT8 X product:
 // dC[a][i][p] with p = 64 c + 16 q + (2 j + h) holding k = 64 c + 8 j + 2 q + h
-// (the order in which the B-tile loader hands k to its four lane groups).
+// (the order in which the B-tile loader hands k to its four lane groups), or
+// p = k when `natural` is set (X from B digit planes).
 __global__ void k_slice_c(const double* __restrict__ C, int64_t nao, int64_t nocc, int s,
-                          const int32_t* __restrict__ f, int ncp, int kp,
+                          const int32_t* __restrict__ f, int ncp, int kp, int natural,
                           int8_t* __restrict__ dC) {
   const int64_t n = (int64_t)ncp * kp;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
@@ -75,7 +76,7 @@ __global__ void k_slice_c(const double* __restrict__ C, int64_t nao, int64_t noc
     const int p = (int)(idx - (int64_t)i * kp);
     const int c = p >> 6, q = (p >> 4) & 3, slot = p & 15;
     const int j = slot >> 1, h = slot & 1;
-    const int64_t k = (int64_t)c * 64 + 8 * j + 2 * q + h;
+    const int64_t k = natural ? p : (int64_t)c * 64 + 8 * j + 2 * q + h;
     uint64_t w = 0;
     if (i < nocc && k < nao) w = digit_word(C[k * nocc + i], f[i]);
     for (int a = 0; a < s; ++a) dC[(int64_t)a * n + idx] = (int8_t)digit_byte(w, a + 1);
@@ -128,9 +129,9 @@ hipError_t launch_slice_rows(hipStream_t st, const double* A, int64_t rows, int6
 }
 
 hipError_t launch_slice_c(hipStream_t st, const double* C, int64_t nao, int64_t nocc, int s,
-                          const int32_t* f, int ncp, int kp, int8_t* dC) {
+                          const int32_t* f, int ncp, int kp, int natural, int8_t* dC) {
   hipLaunchKernelGGL(k_slice_c, dim3(grid_for((int64_t)ncp * kp, 256)), dim3(256), 0, st, C,
-                     nao, nocc, s, f, ncp, kp, dC);
+                     nao, nocc, s, f, ncp, kp, natural, dC);
   return hipGetLastError();
 }
 
