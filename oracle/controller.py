@@ -18,7 +18,10 @@ Pins (tests/test_oracle_controller.py): central finite differences of the
 loss in every parameter tensor; zero weights give y = b3 and zero gradients
 above the last layer; a one-step Adam move equals lr * sign(g) for any g;
 Adam on a convex quadratic converges to its minimiser; the slice choice is
-the smallest passing s, is monotone in the target and falls back to FP64.
+the smallest passing s, is monotone in the target and falls back to FP64; the
+per-block allocation returns the reference count for identical blocks, meets
+the budget with no more digit products than the uniform choice, leaves
+negligible blocks at one slice and steps over plateaus of the predictions.
 """
 import numpy as np
 
@@ -157,3 +160,46 @@ def block_errors(B, C, occ=2.0, pblk=64, slices=range(1, 9)):
             err = np.max(np.abs(Kb - Kb64)) / nK if nK > 0 else 0.0
             out[bi, s - 1] = _log10(err)
     return out
+
+
+def allocate(pred, s_ref, slack=1.0):
+    """Per-block slice counts meeting the predicted error of a uniform s_ref.
+
+    pred [nb][8]: predicted log10 errors per block for s = 1..8, taken
+    non-increasing in s (running minimum).  Budget = slack * sum_b err_b(s_ref).
+    Greedy: from s = 1 everywhere, repeatedly move the block with the largest
+    predicted error drop per added digit product (s -> s' costs
+    s'(s'+1)/2 - s(s+1)/2 products) to s', the next count with a strictly
+    smaller predicted error, until the predicted total meets the budget.
+    s_ref = 0 -> all 0.
+    """
+    pred = np.asarray(pred, dtype=np.float32).astype(np.float64)
+    nb = pred.shape[0]
+    if s_ref == 0:
+        return np.zeros(nb, dtype=np.int64)
+    err = np.minimum.accumulate(10.0 ** pred, axis=1)
+    budget = 0.0
+    for b in range(nb):                 # sums in block order, like the library
+        budget += err[b, s_ref - 1]
+    budget *= slack
+    s = np.ones(nb, dtype=np.int64)
+    while True:
+        total = 0.0
+        for b in range(nb):             # the predicted total, in block order
+            total += err[b, s[b] - 1]
+        if not total > budget:
+            break
+        best, gain, best_to = -1, 0.0, 0
+        for b in range(nb):
+            to = s[b] + 1
+            while to <= N_OUT and not err[b, to - 1] < err[b, s[b] - 1]:
+                to += 1
+            if to > N_OUT:
+                continue
+            g = (err[b, s[b] - 1] - err[b, to - 1]) / (to * (to + 1) // 2 - s[b] * (s[b] + 1) // 2)
+            if best < 0 or g > gain:
+                best, gain, best_to = b, g, to
+        if best < 0:
+            break
+        s[best] = best_to
+    return s

@@ -131,3 +131,49 @@ def test_features_shape_and_bias():
                            5, 4, 2, 3, 1, 4)
     assert f.shape == (16,)
     assert f[-1] == 1.0 and f[3] == 0.2 and f[9] == pytest.approx(-8.0)
+
+
+def _slopes(nb, seed=0):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-12, 0, nb)                 # block scale (log10 err at s = 0)
+    return a[:, None] - 2.4 * np.arange(1, 9)[None, :]   # ~8 bits per slice
+
+
+def test_allocate_identical_blocks_give_the_reference():
+    pred = np.tile(-2.4 * np.arange(1, 9), (10, 1))
+    for s_ref in (1, 3, 6, 8):
+        assert list(ctl.allocate(pred, s_ref)) == [s_ref] * 10
+    assert list(ctl.allocate(pred, 0)) == [0] * 10
+
+
+def test_allocate_meets_budget_with_less_work():
+    pred = _slopes(40)
+    err = 10.0 ** pred
+    for s_ref in (3, 5, 7):
+        s = ctl.allocate(pred, s_ref)
+        assert err[np.arange(40), s - 1].sum() <= err[:, s_ref - 1].sum() * (1 + 1e-12)
+        work = (s * (s + 1) // 2).sum()
+        assert work <= 40 * s_ref * (s_ref + 1) // 2
+    # blocks six decades below the others stay at one slice
+    pred2 = np.vstack([_slopes(8), _slopes(8) - 20.0])
+    s = ctl.allocate(pred2, 4)
+    assert np.all(s[8:] == 1)
+
+
+def test_allocate_non_monotone_predictions_use_running_minimum():
+    pred = np.tile(-2.4 * np.arange(1, 9), (3, 1))
+    pred[1, 4] = 5.0   # a spurious bump at s = 5 is ignored
+    s = ctl.allocate(pred, 6)
+    assert list(s) == [6, 6, 6]
+
+
+def test_library_allocate_matches_oracle():
+    from paper_2601_08077_amd.binding import df_controller_allocate
+    rng = np.random.default_rng(9)
+    for trial in range(20):
+        nb = int(rng.integers(1, 100))
+        pred = (_slopes(nb, trial) + rng.normal(0, 0.3, (nb, 8))).astype(np.float32)
+        for s_ref in (0, 2, 5, 8):
+            for slack in (1.0, 2.0):
+                got = df_controller_allocate(pred, s_ref, slack)
+                assert got == list(ctl.allocate(pred, s_ref, slack))
