@@ -42,8 +42,12 @@ def make_orbitals(rng, nao, nocc, occ=2.0):
     return C, D
 
 
-def make_problem(nao, naux, nocc, L=12.0, seed=0, row_scale=False, occ=2.0):
-    """Host-side problem: dict(B (naux, nao, nao), C, D, r, occ)."""
+def make_problem(nao, naux, nocc, L=12.0, seed=0, row_scale=False, occ=2.0, block_scale=0):
+    """Host-side problem: dict(B (naux, nao, nao), C, D, r, occ).
+
+    block_scale = w > 0 (instead of row_scale): one factor 10^U(-w, 0) per
+    block of 64 consecutive aux indices (aux functions grouped by size, as
+    when they are sorted by shell), drawn after C."""
     rng = np.random.default_rng(seed)
     G = rng.standard_normal((naux, nao, nao))
     dmn, dp = _decay(nao, naux, L)
@@ -54,6 +58,10 @@ def make_problem(nao, naux, nocc, L=12.0, seed=0, row_scale=False, occ=2.0):
     if row_scale:
         r = 10.0 ** rng.uniform(-6.0, 0.0, naux)
         B *= r[:, None, None]
+    elif block_scale:
+        nbk = (naux + 63) // 64
+        r = np.repeat(10.0 ** rng.uniform(-float(block_scale), 0.0, nbk), 64)[:naux]
+        B *= r[:, None, None]
     return dict(B=np.ascontiguousarray(B), C=C, D=D, r=r, occ=occ)
 
 
@@ -62,17 +70,20 @@ def config0(seed=0):
 
 
 def make_problem_device(nao, naux, nocc, L=12.0, seed=0, row_scale=False, occ=2.0,
-                        device="cuda", chunk=128):
+                        device="cuda", chunk=128, block_scale=0):
     """Device-side problem (torch float64 tensors on ``device``).
 
     G is drawn with ``torch.Generator(device).manual_seed(seed)`` one aux chunk
     of ``chunk`` rows at a time; C, D and r come from the NumPy stream of
-    ``seed`` (M first, then r).
+    ``seed`` (M first, then r; block_scale as in make_problem).
     """
     import torch
     rng = np.random.default_rng(seed)
     C, D = make_orbitals(rng, nao, nocc, occ)
     r = 10.0 ** rng.uniform(-6.0, 0.0, naux) if row_scale else None
+    if r is None and block_scale:
+        nbk = (naux + 63) // 64
+        r = np.repeat(10.0 ** rng.uniform(-float(block_scale), 0.0, nbk), 64)[:naux]
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
     dmn, dp = _decay(nao, naux, L)
@@ -144,3 +155,35 @@ def raw_three_index_device(nao, naux, L=12.0, seed=0, device="cuda", chunk=128):
         T[p0:p1].copy_(G)
         del G
     return T.reshape(naux, nao * nao)
+
+
+def mlp_init(seed=0, n_in=16, n_hidden=64, n_out=8):
+    """Initial perceptron parameters, FP32, packed W1, b1, W2, b2, W3, b3:
+    W ~ N(0, 2 / fan_in) (He), biases 0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fi, fo in ((n_in, n_hidden), (n_hidden, n_hidden), (n_hidden, n_out)):
+        parts.append(rng.standard_normal((fi, fo)) * np.sqrt(2.0 / fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+
+
+def batch_indices(n, batch, steps, seed=0):
+    """Row indices of `steps` training batches: consecutive slices of seeded
+    permutations of range(n) (a fresh permutation per pass), int32 [steps][batch]."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((steps, batch), dtype=np.int32)
+    perm, pos = rng.permutation(n), 0
+    for s in range(steps):
+        for j in range(batch):
+            if pos == n:
+                perm, pos = rng.permutation(n), 0
+            out[s, j] = perm[pos]
+            pos += 1
+    return out
+
+
+def spot_blocks(nb, count, iteration, seed=0):
+    """Blocks checked in FP64 at one iteration: `count` distinct draws."""
+    rng = np.random.default_rng([seed, iteration])
+    return [int(b) for b in rng.choice(nb, size=min(count, nb), replace=False)]

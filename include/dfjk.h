@@ -177,6 +177,25 @@ int df_build_jk_sliced(df_ctx* ctx, const int8_t* b_dig, int planes, const int32
                        const double* D, double* J, double* K, double* energies,
                        double* err_bound);
 
+/* Block screening of B (Sec. 2.1: negligible shell pairs are dropped and B
+ * inherits the sparsity).  With shell blocks of `blk` consecutive basis
+ * functions (blk divides 64; nao <= 4096), block (M, N) is kept iff
+ * sqrt(sum_P sum_{mu in M, nu in N} B[P][mu][nu]^2) >= tau (FP64).  df_screen
+ * writes mask[M][N] (uint8, 1 = kept; nblk = ceil(nao / blk)), the optional
+ * norms[M][N], and chunks[mu] (uint64: bit c set iff a kept block meets row
+ * mu in nu = 64c .. 64c + 63), and sets the dropped entries of B to zero IN
+ * PLACE (B is modified).  Uses the context's scratch, or, for
+ * nblk * nao * 8 > 8 MiB, a workspace of at least that size.
+ * df_set_screening hands mask / chunks (caller-owned, kept until reset with
+ * NULL) to the following df_build_jk / df_build_x calls with this nao: X and
+ * the row dots of rho skip the zero nu chunks, J skips the dropped blocks.
+ * The results equal the dense build of the zeroed B bit for bit (only sums of
+ * exact zeros are skipped); with a B not zeroed by that mask they differ. */
+int df_screen(df_ctx* ctx, double* B, int64_t naux, int64_t nao, int blk, double tau,
+              uint8_t* mask, uint64_t* chunks, double* norms);
+int df_set_screening(df_ctx* ctx, const uint8_t* mask, const uint64_t* chunks, int blk,
+                     int64_t nao);
+
 /* Metric Cholesky (Sec. 2.1, Eq. 2): W [n][n] symmetric positive definite is
  * overwritten in place by L (lower triangle; the upper triangle is set to 0)
  * with L L^T = W, in FP64.  A non-positive pivot sets the DF_ENOTSPD device
@@ -209,6 +228,79 @@ int df_density(df_ctx* ctx, const double* C, int64_t nao, int64_t nocc, double o
 int df_rule_level(double de_rel);
 int df_rule_next_level(int level, double e_prev, double e_now);
 int df_rule_slices(int level, int fp64_below_level);
+
+/* ---- Learned slice controller (per-aux-block precision; extends the
+ * per-iteration rule of Sec. 3.2 / Table 1 along the outlook of Sec. 6) ----
+ * The context owns an 8 MiB device scratch for these calls (allocated by
+ * df_create); calls on one context are ordered by its stream.
+ *
+ * df_block_stats: out[seg] = (max |A - A2|, sum (A - A2)^2) over consecutive
+ *   segments of `seglen` elements of A[n] (the last one ragged); A2 may be
+ *   NULL (then A alone).  nseg = ceil(n / seglen) <= 2^19.  FP64.
+ * df_x_block_stats: the same over the aux blocks of X left in the workspace by
+ *   the last df_build_jk of this shape (blocked layout: one segment per block
+ *   of pblk aux indices); out[nblocks][2].
+ * df_controller_features: feat[nblocks][16] (FP32) of one iteration from
+ *   bstats [nblocks][2] (df_block_stats of B per aux block), xstats
+ *   [nblocks][2] (df_x_block_stats of the previous iteration), dstat[2]
+ *   (D_k - D_k-1), cstat[2] (C_k), kstat[2] (K_k-1) and host_scalars[8] =
+ *   {k, n_iter, dE_rel(k-1), target, nao, naux, nocc, plain-rule s}:
+ *     log2 max|B_b|, log2 |B_b|_F, log10 |D_k - D_k-1|_F, k / n_iter,
+ *     log10 dE_rel, log2 max|C_k|, log2 max|X_b|, log2 |X_b|_F, log2 |K_k-1|_F,
+ *     log10 target, log2 nao, log2 naux, log2 nocc, s_plain / 8, b / nblocks, 1
+ *   (log of 0 is written as -1100 for log2 and -330 for log10).
+ * df_mlp_nparams: 5768, the FP32 parameter count, packed row-major as
+ *   W1[16][64], b1[64], W2[64][64], b2[64], W3[64][8], b3[8].
+ * df_mlp_forward: y[n][8] = ReLU(ReLU(x W1 + b1) W2 + b2) W3 + b3, x[n][16].
+ * df_mlp_train_step: one Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8,
+ *   bias-corrected with the 1-based `step`) on the masked mean squared error
+ *   sum m (y - t)^2 / max(sum m, 1) over the batch rows idx[0..n-1] of
+ *   x[.][16], t[.][8], mask[.][8] (idx NULL: rows 0..n-1).  params, adam_m,
+ *   adam_v [5768] are updated in place; loss (device float, may be NULL)
+ *   receives the batch loss before the update.  n <= 11000.  Gradient partials
+ *   of 32-row tiles are summed in tile order (deterministic).
+ * df_choose_slices: s_out[b] (device int32) = the smallest s in 1..8 with
+ *   pred[b][s-1] <= log10(target) (compared in FP64), else 0 (native FP64).
+ * df_block_partials: copies the per-block K partials K_b (lower triangles
+ *   valid, without occ) of the last df_build_jk with block precision set into
+ *   out[nblocks][nao][nao].
+ * df_block_errors: err[b] = |occ| max_{mu >= nu} |K_b - kref_b| / kfro for the
+ *   partials of the last df_build_jk with block precision set (kref as written
+ *   by df_block_partials, e.g. of an all-FP64 build).
+ * df_spot_check: the FP64 check of sampled blocks: for each host_blocks[i],
+ *   recomputes K_b in native FP64 from B and C and writes
+ *   err[i] = |occ| max |K_b - K_b(FP64)| / kfro for the partials of the last
+ *   df_build_jk with block precision set.  Needs the build's workspace. */
+/* df_controller_allocate (host only, no GPU work): per-block slice counts at
+ * the accuracy of one reference count.  pred [nblocks][8] (host) holds the
+ * predicted log10 errors of every block for s = 1..8 (taken non-increasing in
+ * s); the error budget is slack * sum_b 10^pred[b][s_ref-1], the predicted
+ * error of all blocks at s_ref.  Starting from s = 1 everywhere, the block
+ * whose move to its next count with a strictly smaller predicted error
+ * removes the most error per added digit product (s -> s' adds
+ * s'(s'+1)/2 - s(s+1)/2 products) is moved, until the predicted total meets
+ * the budget (or no block can improve).  s_ref == 0 gives 0 (native FP64)
+ * for all. */
+int df_controller_allocate(const float* pred, int64_t nblocks, int s_ref, double slack,
+                           int32_t* s_out);
+int df_block_stats(df_ctx* ctx, const double* A, const double* A2, int64_t n, int64_t seglen,
+                   double* out);
+int df_x_block_stats(df_ctx* ctx, int64_t naux, int64_t nao, int64_t nocc, double* out);
+int df_controller_features(df_ctx* ctx, const double* bstats, const double* xstats,
+                           const double* dstat, const double* cstat, const double* kstat,
+                           const double* host_scalars, int64_t nblocks, float* feat);
+int df_mlp_nparams(void);
+int df_mlp_forward(df_ctx* ctx, const float* params, const float* x, int64_t n, float* y);
+int df_mlp_train_step(df_ctx* ctx, float* params, float* adam_m, float* adam_v, int64_t step,
+                      const float* x, const float* t, const float* mask, const int32_t* idx,
+                      int64_t n, float lr, float* loss);
+int df_choose_slices(df_ctx* ctx, const float* pred, int64_t n, double target, int32_t* s_out);
+int df_block_partials(df_ctx* ctx, int64_t naux, int64_t nao, int64_t nocc, double* out);
+int df_block_errors(df_ctx* ctx, int64_t naux, int64_t nao, int64_t nocc, double occ,
+                    const double* kref, double kfro, double* err);
+int df_spot_check(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* C,
+                  int64_t nocc, double occ, double kfro, const int32_t* host_blocks, int nsample,
+                  double* err);
 
 /* Device status word (0, DF_ENONFINITE or DF_ENOTSPD) accumulated since the last call;
  * synchronises the context stream and clears the word. */

@@ -42,6 +42,27 @@ SIGNATURES = {
     "df_build_jk_sliced": (_int, [_c_void_p, _c_void_p, _int, _c_void_p, _i64, _i64, _c_void_p,
                                   _i64, ctypes.c_double, _c_void_p, _c_void_p, _c_void_p,
                                   _c_void_p, _c_void_p]),
+    "df_block_stats": (_int, [_c_void_p, _c_void_p, _c_void_p, _i64, _i64, _c_void_p]),
+    "df_x_block_stats": (_int, [_c_void_p, _i64, _i64, _i64, _c_void_p]),
+    "df_controller_features": (_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                      _c_void_p, ctypes.POINTER(ctypes.c_double), _i64,
+                                      _c_void_p]),
+    "df_mlp_nparams": (_int, []),
+    "df_mlp_forward": (_int, [_c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p]),
+    "df_mlp_train_step": (_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p,
+                                 _c_void_p, _c_void_p, _c_void_p, _i64, ctypes.c_float,
+                                 _c_void_p]),
+    "df_choose_slices": (_int, [_c_void_p, _c_void_p, _i64, ctypes.c_double, _c_void_p]),
+    "df_block_partials": (_int, [_c_void_p, _i64, _i64, _i64, _c_void_p]),
+    "df_block_errors": (_int, [_c_void_p, _i64, _i64, _i64, ctypes.c_double, _c_void_p,
+                               ctypes.c_double, _c_void_p]),
+    "df_spot_check": (_int, [_c_void_p, _c_void_p, _i64, _i64, _c_void_p, _i64, ctypes.c_double,
+                             ctypes.c_double, ctypes.POINTER(ctypes.c_int32), _int, _c_void_p]),
+    "df_controller_allocate": (_int, [ctypes.POINTER(ctypes.c_float), _i64, _int, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "df_screen": (_int, [_c_void_p, _c_void_p, _i64, _i64, _int, ctypes.c_double, _c_void_p,
+                         _c_void_p, _c_void_p]),
+    "df_set_screening": (_int, [_c_void_p, _c_void_p, _c_void_p, _int, _i64]),
     "df_get_status": (_int, [_c_void_p]),
     "df_last_error": (ctypes.c_char_p, [_c_void_p]),
     "df_metric_cholesky": (_int, [_c_void_p, _c_void_p, _i64]),
@@ -67,6 +88,9 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_2601_08077_amd.build` (hipcc, gfx950)")
+    # torch's HIP runtime must be the one in the process before the library
+    # binds to libamdhip64 (both carry the same soname): import it first.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -200,6 +224,61 @@ class Context:
                                                 _ptr(D), _ptr(J), _ptr(K), _ptr(energies),
                                                 _ptr(err_bound)), "df_build_jk_sliced")
 
+    # -- learned slice controller -------------------------------------------------
+    def df_block_stats(self, A, out, seglen, A2=None):
+        self._check(self.lib.df_block_stats(self.h, _ptr(A), _ptr(A2), A.numel(), int(seglen),
+                                            _ptr(out)), "df_block_stats")
+
+    def df_x_block_stats(self, naux, nao, nocc, out):
+        self._check(self.lib.df_x_block_stats(self.h, naux, nao, nocc, _ptr(out)),
+                    "df_x_block_stats")
+
+    def df_controller_features(self, bstats, xstats, dstat, cstat, kstat, scalars, feat):
+        sc = (ctypes.c_double * 8)(*[float(v) for v in scalars])
+        self._check(self.lib.df_controller_features(self.h, _ptr(bstats), _ptr(xstats),
+                                                    _ptr(dstat), _ptr(cstat), _ptr(kstat), sc,
+                                                    feat.shape[0], _ptr(feat)),
+                    "df_controller_features")
+
+    def df_mlp_forward(self, params, x, y):
+        self._check(self.lib.df_mlp_forward(self.h, _ptr(params), _ptr(x), x.shape[0], _ptr(y)),
+                    "df_mlp_forward")
+
+    def df_mlp_train_step(self, params, m, v, step, x, t, mask, idx, n, lr, loss=None):
+        self._check(self.lib.df_mlp_train_step(self.h, _ptr(params), _ptr(m), _ptr(v), int(step),
+                                               _ptr(x), _ptr(t), _ptr(mask), _ptr(idx), int(n),
+                                               float(lr), _ptr(loss)), "df_mlp_train_step")
+
+    def df_choose_slices(self, pred, target, s_out):
+        self._check(self.lib.df_choose_slices(self.h, _ptr(pred), pred.shape[0], float(target),
+                                              _ptr(s_out)), "df_choose_slices")
+
+    def df_block_partials(self, naux, nao, nocc, out):
+        self._check(self.lib.df_block_partials(self.h, naux, nao, nocc, _ptr(out)),
+                    "df_block_partials")
+
+    def df_block_errors(self, naux, nao, nocc, occ, kref, kfro, err):
+        self._check(self.lib.df_block_errors(self.h, naux, nao, nocc, float(occ), _ptr(kref),
+                                             float(kfro), _ptr(err)), "df_block_errors")
+
+    def df_spot_check(self, B, C, occ, kfro, blocks, err):
+        naux, nao = B.shape[0], B.shape[1]
+        arr = (ctypes.c_int32 * len(blocks))(*[int(b) for b in blocks])
+        self._check(self.lib.df_spot_check(self.h, _ptr(B), naux, nao, _ptr(C), C.shape[1],
+                                           float(occ), float(kfro), arr, len(blocks), _ptr(err)),
+                    "df_spot_check")
+
+    def df_screen(self, B, blk, tau, mask, chunks, norms=None):
+        """Zeroes the dropped shell blocks of B in place; mask uint8 [nblk][nblk],
+        chunks int64 [nao] (bit patterns), norms float64 [nblk][nblk] or None."""
+        naux, nao = B.shape[0], B.shape[1]
+        self._check(self.lib.df_screen(self.h, _ptr(B), naux, nao, int(blk), float(tau),
+                                       _ptr(mask), _ptr(chunks), _ptr(norms)), "df_screen")
+
+    def df_set_screening(self, mask, chunks, blk, nao):
+        self._check(self.lib.df_set_screening(self.h, _ptr(mask), _ptr(chunks), int(blk), int(nao)),
+                    "df_set_screening")
+
     def df_metric_cholesky(self, W):
         """In place: the lower triangle of W becomes L (L L^T = W), upper set to 0."""
         self._check(self.lib.df_metric_cholesky(self.h, _ptr(W), W.shape[0]), "df_metric_cholesky")
@@ -233,6 +312,23 @@ class Context:
         self._check(self.lib.df_debug_slice_gemm_i32(self.h, _ptr(a_dig), _ptr(b_dig), m, n, k,
                                                      int(s), _ptr(partials)),
                     "df_debug_slice_gemm_i32")
+
+
+def df_mlp_nparams():
+    return load().df_mlp_nparams()
+
+
+def df_controller_allocate(pred, s_ref, slack=1.0):
+    """pred: host float array [nblocks][8] of predicted log10 errors; returns a list of s."""
+    import numpy as np
+    p = np.ascontiguousarray(pred, dtype=np.float32)
+    nb = p.shape[0]
+    out = (ctypes.c_int32 * nb)()
+    rc = load().df_controller_allocate(p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), nb,
+                                       int(s_ref), float(slack), out)
+    if rc != DF_OK:
+        raise DFError(rc, "df_controller_allocate: bad arguments")
+    return list(out)
 
 
 def df_prepare_b_size(naux, nao, planes):

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdfjk.so")
-SOURCES = ["api.hip", "slicing.hip", "int8_gemm.hip", "fp64_gemm.hip", "jk.hip", "metric.hip", "sliced.hip"]
+SOURCES = ["api.hip", "slicing.hip", "int8_gemm.hip", "fp64_gemm.hip", "jk.hip", "metric.hip", "sliced.hip", "controller.hip", "screen.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 GPU_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

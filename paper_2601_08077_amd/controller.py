@@ -1,0 +1,253 @@
+"""Learned per-block slice controller (the per-iteration rule of Sec. 3.2 /
+Table 1 taken down to aux blocks, along the outlook of Sec. 6).
+
+Sample generation, GPU training and the controlled sequence of J/K builds.
+Every numerical step runs in libdfjk: block statistics and features, the
+16 -> 64 -> 64 -> 8 perceptron (forward, backward, Adam), the per-block
+allocation, the per-block build and the FP64 spot check.  This module holds
+device buffers (torch), moves the few host values the sequence logic needs
+and keeps the records.
+
+A prediction is log10(max |K_b(s) - K_b| / ||K||_F) for s = 1..8.  At each
+iteration the plain rule still names a reference count s_ref; the controller
+gives every block the count that keeps the predicted total error at or below
+that of s_ref everywhere, with the fewest digit products
+(df_controller_allocate).  Sampled blocks are recomputed in FP64
+(df_spot_check); a block whose error exceeds `margin` times its prediction
+sends the iteration back to the plain rule (uniform s_ref).
+"""
+import math
+
+import numpy as np
+
+from . import binding
+
+ACCURACY = {4: 2.0 ** -23, 3: 2.0 ** -31, 2: 2.0 ** -39, 1: 2.0 ** -47, 0: 2.0 ** -52}
+
+
+class _Buffers:
+    def __init__(self, B, naux, nao, nocc, pblk):
+        import torch
+        dev = B.device
+        f64 = torch.float64
+        self.nb = (naux + pblk - 1) // pblk
+        self.D = torch.empty((nao, nao), dtype=f64, device=dev)
+        self.Dprev = torch.empty_like(self.D)
+        self.J = torch.empty_like(self.D)
+        self.K = torch.empty_like(self.D)
+        self.Kprev = torch.zeros_like(self.D)
+        self.en = torch.empty(2, dtype=f64, device=dev)
+        self.eb = torch.empty(1, dtype=f64, device=dev)
+        self.bstats = torch.empty((self.nb, 2), dtype=f64, device=dev)
+        self.xstats = torch.zeros((self.nb, 2), dtype=f64, device=dev)
+        self.dstat = torch.zeros((1, 2), dtype=f64, device=dev)
+        self.cstat = torch.zeros((1, 2), dtype=f64, device=dev)
+        self.kstat = torch.zeros((1, 2), dtype=f64, device=dev)
+        self.feat = torch.empty((self.nb, 16), dtype=torch.float32, device=dev)
+        self.pred = torch.empty((self.nb, 8), dtype=torch.float32, device=dev)
+        self.err = torch.empty(self.nb, dtype=f64, device=dev)
+        self.kfro = torch.empty((1, 2), dtype=f64, device=dev)
+
+
+class BlockFeatures:
+    """Per-run feature state: B's block statistics (once), X and D of the
+    previous iteration, K of the previous iteration."""
+
+    def __init__(self, ctx, B, naux, nao, nocc, pblk=64):
+        self.ctx, self.B = ctx, B
+        self.naux, self.nao, self.nocc, self.pblk = naux, nao, nocc, pblk
+        self.buf = _Buffers(B, naux, nao, nocc, pblk)
+        ctx.df_block_stats(B, self.buf.bstats, pblk * nao * nao)
+        self.have_prev = False
+
+    def features(self, C, D, k, n_iter, de_rel, target, plain_s):
+        b = self.buf
+        ctx = self.ctx
+        ctx.df_block_stats(C, b.cstat, C.shape[0] * C.shape[1])
+        ctx.df_block_stats(D, b.dstat, D.numel(), A2=b.Dprev if self.have_prev else D)
+        ctx.df_block_stats(b.Kprev, b.kstat, b.Kprev.numel())
+        sc = [k, n_iter, de_rel if de_rel == de_rel else 0.0, target, self.nao, self.naux,
+              self.nocc, plain_s]
+        ctx.df_controller_features(b.bstats, b.xstats, b.dstat, b.cstat, b.kstat, sc, b.feat)
+        return b.feat
+
+    def after_build(self, D, K):
+        """Record X (workspace of the build just made), D and K for the next iteration."""
+        self.ctx.df_x_block_stats(self.naux, self.nao, self.nocc, self.buf.xstats)
+        self.buf.Dprev.copy_(D)
+        self.buf.Kprev.copy_(K)
+        self.have_prev = True
+
+
+def _energy(en):
+    e = en.cpu().numpy()
+    return float(e[0] + e[1])
+
+
+def _rel_change(e_prev, e_now):
+    if e_prev is None:
+        return float("nan")
+    d = e_now - e_prev
+    return abs(d) if e_now == 0 else abs(d / e_now)
+
+
+def collect_samples(ctx, B, b_exp, orbitals, occ=2.0, pblk=64, slices=range(1, 9)):
+    """Training samples of one sequence of orbitals: for every iteration and
+    block, the 16 features and the measured log10 block errors at each s in
+    `slices` (mask 1 where measured and non-zero).  Returns float32 arrays
+    x [n][16], t [n][8], m [n][8]."""
+    import torch
+    naux, nao = B.shape[0], B.shape[1]
+    nocc = orbitals[0].shape[1]
+    ctx.df_set_pblk(pblk)
+    fs = BlockFeatures(ctx, B, naux, nao, nocc, pblk)
+    b = fs.buf
+    nb = b.nb
+    kref = torch.empty((nb, nao, nao), dtype=torch.float64, device=B.device)
+    xs, ts, ms = [], [], []
+    level, e_hist = 4, []
+    for k, C in enumerate(orbitals):
+        ctx.df_density(C, occ, b.D)
+        de = _rel_change(e_hist[-2], e_hist[-1]) if len(e_hist) >= 2 else float("nan")
+        s_plain = binding.df_rule_slices(level, 0)
+        feat = fs.features(C, b.D, k, len(orbitals), de, ACCURACY[level], s_plain)
+        x = feat.cpu().numpy().copy()
+        # FP64 reference partials
+        ctx.df_set_block_precision([0] * nb)
+        ctx.ensure_workspace(naux, nao, nocc)
+        ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb)
+        ctx.df_block_partials(naux, nao, nocc, kref)
+        ctx.df_block_stats(b.K, b.kfro, b.K.numel())
+        e64 = _energy(b.en)
+        kfro = math.sqrt(float(b.kfro.cpu()[0, 1]))
+        K64 = b.K.clone()
+        fs.after_build(b.D, K64)
+        t = np.zeros((nb, 8), dtype=np.float32)
+        m = np.zeros((nb, 8), dtype=np.float32)
+        for s in slices:
+            ctx.df_set_block_precision([s] * nb)
+            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb)
+            ctx.df_block_errors(naux, nao, nocc, occ, kref, kfro, b.err)
+            err = b.err.cpu().numpy()
+            ok = err > 0
+            t[ok, s - 1] = np.log10(err[ok])
+            m[ok, s - 1] = 1.0
+        xs.append(x)
+        ts.append(t)
+        ms.append(m)
+        e_hist.append(e64)
+        if len(e_hist) >= 2:
+            level = binding.df_rule_next_level(level, e_hist[-2], e_hist[-1])
+    ctx.df_set_block_precision(None)
+    return np.concatenate(xs), np.concatenate(ts), np.concatenate(ms)
+
+
+def train(ctx, x, t, m, steps=2000, batch=1024, lr=1e-3, seed=0, log_every=0):
+    """Adam on the masked squared error, on the GPU.  Returns (params, losses)."""
+    import torch
+    import dfinputs
+    n = x.shape[0]
+    batch = min(batch, n)
+    dx = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    dt = torch.from_numpy(np.ascontiguousarray(t, dtype=np.float32)).cuda()
+    dm = torch.from_numpy(np.ascontiguousarray(m, dtype=np.float32)).cuda()
+    params = torch.from_numpy(dfinputs.mlp_init(seed)).cuda()
+    m1 = torch.zeros_like(params)
+    m2 = torch.zeros_like(params)
+    idx = torch.from_numpy(dfinputs.batch_indices(n, batch, steps, seed)).cuda()
+    loss = torch.empty(steps, dtype=torch.float32, device="cuda")
+    for step in range(steps):
+        ctx.df_mlp_train_step(params, m1, m2, step + 1, dx, dt, dm, idx[step], batch, lr,
+                              loss[step:step + 1])
+    losses = loss.cpu().numpy()
+    return params, losses
+
+
+def evaluate(ctx, params, x, t, m):
+    """Masked RMS error (in decades) of the predictions on (x, t, m)."""
+    import torch
+    dx = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    y = torch.empty((x.shape[0], 8), dtype=torch.float32, device="cuda")
+    ctx.df_mlp_forward(params, dx, y)
+    yh = y.cpu().numpy()
+    r = (yh - t) * m
+    return float(np.sqrt((r * r).sum() / max(m.sum(), 1.0)))
+
+
+def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below_level=0,
+                   spot=2, margin=10.0, judge=False, seed=0):
+    """The controlled sequence.  Per iteration: plain-rule reference count,
+    features, prediction, per-block allocation, build, FP64 spot check (and
+    fallback to the uniform reference count).  Returns per-iteration records
+    with the time, the per-block counts and their digit-product work."""
+    import torch
+    import dfinputs
+    naux, nao = B.shape[0], B.shape[1]
+    nocc = orbitals[0].shape[1]
+    ctx.df_set_pblk(pblk)
+    fs = BlockFeatures(ctx, B, naux, nao, nocc, pblk)
+    b = fs.buf
+    nb = b.nb
+    spot_err = torch.empty(max(spot, 1), dtype=torch.float64, device=B.device)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    K64 = torch.empty_like(b.K) if judge else None
+    en64 = torch.empty_like(b.en) if judge else None
+    level, e_prev, e_prev2 = 4, None, None
+    recs = []
+    for k, C in enumerate(orbitals):
+        s_ref = binding.df_rule_slices(level, fp64_below_level)
+        ctx.df_density(C, occ, b.D)
+        ev0.record()
+        fallback = False
+        if s_ref == 0:
+            sb = [0] * nb
+            ctx.df_set_block_precision(sb)
+            ctx.ensure_workspace(naux, nao, nocc)
+            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb)
+            pred_h = None
+        else:
+            de = _rel_change(e_prev2, e_prev)
+            feat = fs.features(C, b.D, k, len(orbitals), de, ACCURACY[level], s_ref)
+            ctx.df_mlp_forward(params, feat, b.pred)
+            pred_h = b.pred.cpu().numpy()
+            sb = binding.df_controller_allocate(pred_h, s_ref)
+            ctx.df_set_block_precision(sb)
+            ctx.ensure_workspace(naux, nao, nocc)
+            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb)
+            if spot > 0:
+                ctx.df_block_stats(b.K, b.kfro, b.K.numel())
+                kfro = math.sqrt(float(b.kfro.cpu()[0, 1]))
+                blocks = dfinputs.spot_blocks(nb, spot, k, seed)
+                if kfro > 0:
+                    ctx.df_spot_check(B, C, occ, kfro, blocks, spot_err[:len(blocks)])
+                    se = spot_err[:len(blocks)].cpu().numpy()
+                    for i, blk in enumerate(blocks):
+                        lim = margin * 10.0 ** float(np.min(pred_h[blk, :sb[blk]]))
+                        if se[i] > lim and se[i] > 1e-16:
+                            fallback = True
+            if fallback:
+                sb = [s_ref] * nb
+                ctx.df_set_block_precision(sb)
+                ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb)
+        ev1.record()
+        e_now = _energy(b.en)
+        ms = ev0.elapsed_time(ev1)
+        fs.after_build(b.D, b.K)
+        rec = dict(iteration=k, level=level, s_ref=s_ref, slices=list(sb), fallback=fallback,
+                   work=int(sum(s * (s + 1) // 2 for s in sb)),
+                   work_ref=int(nb * s_ref * (s_ref + 1) // 2), energy=e_now, ms=ms,
+                   err_bound=float(b.eb.cpu()[0]))
+        if judge:
+            ctx.df_set_block_precision([0] * nb)
+            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, K64, en64, b.eb)
+            nrm = float(torch.linalg.norm(K64))
+            rec["k_maxabs_rel_fro"] = float((b.K - K64).abs().max()) / nrm if nrm else 0.0
+            rec["energy_fp64"] = _energy(en64)
+            rec["energy_err"] = e_now - rec["energy_fp64"]
+        recs.append(rec)
+        if e_prev is not None:
+            level = binding.df_rule_next_level(level, e_prev, e_now)
+        e_prev2, e_prev = e_prev, e_now
+    ctx.df_set_block_precision(None)
+    return recs

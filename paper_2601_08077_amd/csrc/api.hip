@@ -29,7 +29,17 @@ struct df_ctx {
   std::vector<int32_t> blk_s;
   int32_t* blk_dev = nullptr;
   size_t blk_cap = 0;
+  // small device scratch of the controller entry points (statistics partials,
+  // perceptron gradient partials), allocated with the context
+  char* aux = nullptr;
+  // screening of B (caller-owned device arrays; null = dense)
+  const uint8_t* scr_mask = nullptr;
+  const unsigned long long* scr_chunks = nullptr;
+  int scr_blk = 8;
+  int64_t scr_nao = 0;
 };
+
+constexpr size_t kAuxBytes = (size_t)8 << 20;
 
 namespace {
 
@@ -49,13 +59,19 @@ int hip_fail(df_ctx* c, hipError_t e, const char* where) {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Every launcher reports hipGetLastError() after its launches, so an error
+// left pending by some earlier runtime call of the host program (not of this
+// library) is cleared on entry instead of being reported as ours.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
 // Shape-derived sizes shared by the workspace query and the build.
 struct Plan {
   int64_t naux, nao, nocc;
   int pblk, nb, nao_pad, kbp, ncp, kp, groups, jsplit;
   int naux_pad, jdsplit;
   size_t off_bexp, off_fcol, off_dC, off_X, off_xmax, off_F, off_Xd, off_rho, off_rowdot,
-      off_Jp, off_Kp, off_bsc, off_esc, off_dD, off_gexp, off_h, off_wd, off_Sj, off_drho, total;
+      off_Jp, off_Kp, off_bsc, off_esc, off_dD, off_gexp, off_h, off_wd, off_Sj, off_drho,
+      off_Xs, off_Ks, off_xsmax, total;
 };
 
 size_t carve(size_t& cur, size_t bytes) {
@@ -82,9 +98,12 @@ Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
   p.groups = std::max(1, std::min(g, p.nb));
   if (!c->blk_s.empty()) p.groups = p.nb;  // per-block precision: one partial per block
   const int64_t nn = nao * nao;
-  const int64_t nch = (nn + 511) / 512;
-  p.jsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, 2048 / std::max<int64_t>(nch, 1)));
-  p.jsplit = (int)std::min<int64_t>(p.jsplit, std::max<int64_t>(naux, 1));
+  {
+    // J: (nao + 1) / 2 row-pair workgroups per aux split; aim at >= 4096 workgroups
+    const int64_t pairs = (nao + 1) / 2;
+    p.jsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4096 + pairs - 1) / pairs));
+    p.jsplit = (int)std::min<int64_t>(p.jsplit, std::max<int64_t>(naux, 1));
+  }
   size_t cur = 0;
   p.off_bexp = carve(cur, (size_t)naux * nao * 4);
   p.off_fcol = carve(cur, (size_t)std::max<int64_t>(nocc, 1) * 4);
@@ -115,6 +134,10 @@ Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
   p.off_wd = carve(cur, (size_t)kMaxSlices * nao * p.naux_pad);
   p.off_Sj = carve(cur, (size_t)kMaxSlices * nn * 8);
   p.off_drho = carve(cur, (size_t)naux * 8 + 8);
+  // FP64 check of sampled blocks: one block of X, one K partial, its row maxima
+  p.off_Xs = carve(cur, (size_t)p.pblk * nao * nocc * 8);
+  p.off_Ks = carve(cur, (size_t)nn * 8);
+  p.off_xsmax = carve(cur, (size_t)nao * 8);
   p.total = cur;
   return p;
 }
@@ -144,6 +167,14 @@ T* at(df_ctx* c, size_t off) {
   return reinterpret_cast<T*>(c->ws + off);
 }
 
+// Chunk and block masks of the screened B when they were set for this nao.
+const unsigned long long* chunks_for(const df_ctx* c, int64_t nao) {
+  return c->scr_chunks && c->scr_nao == nao ? c->scr_chunks : nullptr;
+}
+const uint8_t* mask_for(const df_ctx* c, int64_t nao) {
+  return c->scr_mask && c->scr_nao == nao ? c->scr_mask : nullptr;
+}
+
 // Records the boundary event `idx` (0 = call start, i + 1 = end of stage i)
 // of the current timed call, if timing is on and slots remain.
 void mark(df_ctx* c, int idx) {
@@ -165,7 +196,7 @@ int run_x(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp, const
   DF_HIP(launch_fill_u64(c->stream, xmax, (int64_t)p.nb * p.nao, 0ull), "fill xmax");
   if (s == 0) {
     DF_HIP(launch_x_fp64(c->stream, B, p.naux, (int)p.nao, C, (int)p.nocc, X, 0, xmax, p.pblk,
-                         nullptr, nullptr),
+                         nullptr, nullptr, chunks_for(c, p.nao)),
            "x_fp64");
     return DF_OK;
   }
@@ -174,7 +205,7 @@ int run_x(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp, const
   DF_HIP(launch_col_exp(c->stream, C, p.nao, p.nocc, fcol, c->status), "col_exp");
   DF_HIP(launch_slice_c(c->stream, C, p.nao, p.nocc, s, fcol, p.ncp, p.kp, 0, dC), "slice_c");
   DF_HIP(launch_x_int8(c->stream, s, B, p.naux, (int)p.nao, b_exp, dC, p.ncp, p.kp, fcol,
-                       (int)p.nocc, X, 0, xmax, p.pblk, nullptr, nullptr),
+                       (int)p.nocc, X, 0, xmax, p.pblk, nullptr, nullptr, chunks_for(c, p.nao)),
          "x_int8");
   return DF_OK;
 }
@@ -278,11 +309,12 @@ int xk_stages_blocks(df_ctx* c, const Plan& p, const double* B, const int32_t* b
     double* Xr = X + P0 * nao * nocc;  // the blocked layout keeps each block contiguous
     if (r.s == 0) {
       DF_HIP(launch_x_fp64(st, Bp, P1 - P0, (int)nao, C, (int)nocc, Xr, 1, xmax + r.b0 * nao,
-                           p.pblk, D, rowdot + P0 * nao),
+                           p.pblk, D, rowdot + P0 * nao, chunks_for(c, nao)),
              "x_fp64");
     } else {
       DF_HIP(launch_x_int8(st, r.s, Bp, P1 - P0, (int)nao, b_exp + P0 * nao, dC, p.ncp, p.kp, fcol,
-                           (int)nocc, Xr, 1, xmax + r.b0 * nao, p.pblk, D, rowdot + P0 * nao),
+                           (int)nocc, Xr, 1, xmax + r.b0 * nao, p.pblk, D, rowdot + P0 * nao,
+                           chunks_for(c, nao)),
              "x_int8");
     }
   }
@@ -334,19 +366,30 @@ int common_checks(df_ctx* c, const double* B, int layout, int64_t naux, int64_t 
 extern "C" {
 
 int df_create(df_ctx** ctx, void* hip_stream) {
+  clear_stale_error();
   if (!ctx) return DF_EINVAL;
   *ctx = nullptr;
   df_ctx* c = new df_ctx();
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   hipError_t e = hipMalloc(&c->status, 256);
   if (e != hipSuccess) {
+    fprintf(stderr, "df_create: hipMalloc: %s\n", hipGetErrorString(e));
+    delete c;
+    return DF_EHIP;
+  }
+  e = hipMalloc(&c->aux, kAuxBytes);
+  if (e != hipSuccess) {
+    fprintf(stderr, "df_create: hipMalloc: %s\n", hipGetErrorString(e));
+    (void)hipFree(c->status);
     delete c;
     return DF_EHIP;
   }
   e = launch_fill_i32(c->stream, c->status, 1, 0);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
+    fprintf(stderr, "df_create: status word: %s\n", hipGetErrorString(e));
     (void)hipFree(c->status);
+    (void)hipFree(c->aux);
     delete c;
     return DF_EHIP;
   }
@@ -360,6 +403,7 @@ void df_destroy(df_ctx* c) {
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   (void)hipFree(c->status);
   if (c->blk_dev) (void)hipFree(c->blk_dev);
+  (void)hipFree(c->aux);
   delete c;
 }
 
@@ -387,6 +431,7 @@ int df_set_k_groups(df_ctx* c, int groups) {
 }
 
 int df_set_block_precision(df_ctx* c, const int32_t* host_s, int64_t nblocks) {
+  clear_stale_error();
   if (!c) return DF_EINVAL;
   if (!host_s) {
     c->blk_s.clear();
@@ -432,6 +477,7 @@ int df_set_workspace(df_ctx* c, void* dev_ptr, size_t bytes) {
 
 int df_b_exponents(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao,
                    int32_t* b_exp) {
+  clear_stale_error();
   const int rc = check_shape(c, layout, naux, nao, 1);
   if (rc) return rc;
   if (!B || !b_exp) return fail(c, DF_EINVAL, "null pointer");
@@ -441,6 +487,7 @@ int df_b_exponents(df_ctx* c, const double* B, int layout, int64_t naux, int64_t
 
 int df_slice(df_ctx* c, const double* A, int64_t rows, int64_t cols, int64_t lda, int slices,
              int8_t* digits, int32_t* row_exp) {
+  clear_stale_error();
   if (!c) return DF_EINVAL;
   if (!A || !digits || !row_exp) return fail(c, DF_EINVAL, "null pointer");
   if (rows < 0 || cols < 0 || lda < cols) return fail(c, DF_EINVAL, "bad rows/cols/lda");
@@ -453,6 +500,7 @@ int df_slice(df_ctx* c, const double* A, int64_t rows, int64_t cols, int64_t lda
 
 int df_build_x(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao,
                const int32_t* b_exp, const double* C, int64_t nocc, double* X) {
+  clear_stale_error();
   Plan p;
   int rc = common_checks(c, B, layout, naux, nao, C, nocc, p);
   if (rc) return rc;
@@ -468,6 +516,7 @@ int df_build_x(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao
 int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao,
                 const int32_t* b_exp, const double* C, int64_t nocc, double occ,
                 const double* D, double* J, double* K, double* energies, double* err_bound) {
+  clear_stale_error();
   Plan p;
   int rc = common_checks(c, B, layout, naux, nao, C, nocc, p);
   if (rc) return rc;
@@ -500,11 +549,12 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
     rc = xk_stages_blocks(c, p, B, b_exp, C, D, rowdot, occ, K, &fstride);
     if (rc) return rc;
   } else if (s == 0) {
-    DF_HIP(launch_x_fp64(st, B, naux, (int)nao, C, (int)nocc, X, 1, xmax, p.pblk, D, rowdot),
+    DF_HIP(launch_x_fp64(st, B, naux, (int)nao, C, (int)nocc, X, 1, xmax, p.pblk, D, rowdot,
+                         chunks_for(c, nao)),
            "x_fp64");
   } else {
     DF_HIP(launch_x_int8(st, s, B, naux, (int)nao, b_exp, dC, p.ncp, p.kp, fcol, (int)nocc, X, 1,
-                         xmax, p.pblk, D, rowdot),
+                         xmax, p.pblk, D, rowdot, chunks_for(c, nao)),
            "x_int8");
   }
   if (!per_block) {
@@ -515,7 +565,9 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
   double* rho = at<double>(c, p.off_rho);
   DF_HIP(launch_rho_reduce(st, rowdot, naux, (int)nao, rho), "rho_reduce");
   mark(c, 1 + DF_STAGE_RHO);
-  DF_HIP(launch_j(st, B, naux, (int)nao, rho, p.jsplit, at<double>(c, p.off_Jp), J), "j");
+  DF_HIP(launch_j(st, B, naux, (int)nao, rho, p.jsplit, at<double>(c, p.off_Jp), J,
+                  mask_for(c, nao), c->scr_blk),
+         "j");
   mark(c, 1 + DF_STAGE_J);
   DF_HIP(launch_energies(st, rho, naux, D, K, (int)nao, at<double>(c, p.off_esc), energies),
          "energies");
@@ -537,6 +589,7 @@ int df_prepare_b_size(int64_t naux, int64_t nao, int planes, size_t* bytes) {
 
 int df_prepare_b(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao, int planes,
                  int32_t* b_exp, int8_t* b_dig) {
+  clear_stale_error();
   const int rc = check_shape(c, layout, naux, nao, 1);
   if (rc) return rc;
   if (!B || !b_exp || !b_dig) return fail(c, DF_EINVAL, "null pointer");
@@ -553,6 +606,7 @@ int df_build_jk_sliced(df_ctx* c, const int8_t* b_dig, int planes, const int32_t
                        int64_t naux, int64_t nao, const double* C, int64_t nocc, double occ,
                        const double* D, double* J, double* K, double* energies,
                        double* err_bound) {
+  clear_stale_error();
   int rc = check_shape(c, DF_DENSE, naux, nao, nocc);
   if (rc) return rc;
   const int s = c->slices;
@@ -615,7 +669,215 @@ int df_build_jk_sliced(df_ctx* c, const int8_t* b_dig, int planes, const int32_t
   return DF_OK;
 }
 
+// ---------------------------------------------------------------- controller
+int seg_stats(df_ctx* c, const double* A, const double* A2, int64_t n, int64_t seglen,
+              int64_t rowlen, int64_t last_valid, double* out) {
+  const int64_t nseg = (n + seglen - 1) / seglen;
+  const int64_t cap = (int64_t)(kAuxBytes / 16);
+  if (nseg > cap) return fail(c, DF_EINVAL, "too many segments");
+  const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, cap / nseg));
+  DF_HIP(launch_seg_stats(c->stream, A, A2, n, seglen, rowlen, last_valid,
+                          reinterpret_cast<double*>(c->aux), nsplit, out),
+         "seg_stats");
+  return DF_OK;
+}
+
+int df_block_stats(df_ctx* c, const double* A, const double* A2, int64_t n, int64_t seglen,
+                   double* out) {
+  clear_stale_error();
+  if (!c) return DF_EINVAL;
+  if (!A || !out || n < 1 || seglen < 1) return fail(c, DF_EINVAL, "bad arguments");
+  return seg_stats(c, A, A2, n, seglen, seglen, seglen, out);
+}
+
+int df_x_block_stats(df_ctx* c, int64_t naux, int64_t nao, int64_t nocc, double* out) {
+  clear_stale_error();
+  const int rc = check_shape(c, DF_DENSE, naux, nao, nocc);
+  if (rc) return rc;
+  if (!out) return fail(c, DF_EINVAL, "null out");
+  const Plan p = make_plan(c, naux, nao, nocc);
+  if (!c->ws || c->ws_bytes < p.total) return fail(c, DF_EWORKSPACE, "workspace too small");
+  // blocked X: block b holds rows mu of pblk * nocc entries; the last block
+  // uses only its first (naux - (nb - 1) pblk) * nocc entries of each row
+  const int64_t rowlen = (int64_t)p.pblk * nocc;
+  const int64_t last_valid = (naux - (int64_t)(p.nb - 1) * p.pblk) * nocc;
+  return seg_stats(c, at<double>(c, p.off_X), nullptr, (int64_t)p.nb * rowlen * nao, rowlen * nao,
+                   rowlen, last_valid, out);
+}
+
+int df_controller_features(df_ctx* c, const double* bstats, const double* xstats,
+                           const double* dstat, const double* cstat, const double* kstat,
+                           const double* host_scalars, int64_t nblocks, float* feat) {
+  clear_stale_error();
+  if (!c) return DF_EINVAL;
+  if (!bstats || !xstats || !dstat || !cstat || !kstat || !host_scalars || !feat || nblocks < 1)
+    return fail(c, DF_EINVAL, "bad arguments");
+  CtlScalars sc;
+  sc.iteration = host_scalars[0];
+  sc.n_iter = host_scalars[1];
+  sc.de_rel = host_scalars[2];
+  sc.target = host_scalars[3];
+  sc.nao = host_scalars[4];
+  sc.naux = host_scalars[5];
+  sc.nocc = host_scalars[6];
+  sc.plain_s = host_scalars[7];
+  if (!(sc.n_iter > 0) || !(sc.nao >= 1) || !(sc.naux >= 1) || !(sc.nocc >= 1))
+    return fail(c, DF_EINVAL, "n_iter, nao, naux, nocc must be positive");
+  DF_HIP(launch_features(c->stream, bstats, xstats, dstat, cstat, kstat, sc, (int)nblocks, feat),
+         "features");
+  return DF_OK;
+}
+
+int df_mlp_nparams(void) { return mlp_nparam(); }
+
+int df_mlp_forward(df_ctx* c, const float* params, const float* x, int64_t n, float* y) {
+  clear_stale_error();
+  if (!c) return DF_EINVAL;
+  if (!params || !x || !y || n < 1 || n > ((int64_t)1 << 30)) return fail(c, DF_EINVAL, "bad arguments");
+  DF_HIP(launch_mlp_forward(c->stream, params, x, n, y), "mlp_forward");
+  return DF_OK;
+}
+
+int df_mlp_train_step(df_ctx* c, float* params, float* adam_m, float* adam_v, int64_t step,
+                      const float* x, const float* t, const float* mask, const int32_t* idx,
+                      int64_t n, float lr, float* loss) {
+  clear_stale_error();
+  if (!c) return DF_EINVAL;
+  if (!params || !adam_m || !adam_v || !x || !t || !mask || step < 1 || n < 1)
+    return fail(c, DF_EINVAL, "bad arguments");
+  const int64_t ntiles = (n + 31) / 32;
+  const size_t need = (size_t)ntiles * (mlp_nparam() + 1) * 4 + 256;
+  if (need > kAuxBytes) return fail(c, DF_EINVAL, "batch too large (n <= 11000)");
+  if (!(lr > 0.0f)) return fail(c, DF_EINVAL, "lr must be positive");
+  float* cnt = reinterpret_cast<float*>(c->aux);
+  float* gpart = reinterpret_cast<float*>(c->aux + 256);
+  DF_HIP(launch_mlp_train(c->stream, params, adam_m, adam_v, step, x, t, mask, idx, n, lr, gpart, cnt,
+                          loss),
+         "mlp_train");
+  return DF_OK;
+}
+
+int df_choose_slices(df_ctx* c, const float* pred, int64_t n, double target, int32_t* s_out) {
+  clear_stale_error();
+  if (!c) return DF_EINVAL;
+  if (!pred || !s_out || n < 1) return fail(c, DF_EINVAL, "bad arguments");
+  if (!(target > 0.0) || isinf(target)) return fail(c, DF_EINVAL, "target must be positive and finite");
+  DF_HIP(launch_choose(c->stream, pred, n, target, s_out), "choose");
+  return DF_OK;
+}
+
+int df_block_partials(df_ctx* c, int64_t naux, int64_t nao, int64_t nocc, double* out) {
+  clear_stale_error();
+  const int rc = check_shape(c, DF_DENSE, naux, nao, nocc);
+  if (rc) return rc;
+  if (!out) return fail(c, DF_EINVAL, "null out");
+  if (c->blk_s.empty()) return fail(c, DF_EINVAL, "block partials exist only with block precision set");
+  const Plan p = make_plan(c, naux, nao, nocc);
+  if (!c->ws || c->ws_bytes < p.total) return fail(c, DF_EWORKSPACE, "workspace too small");
+  DF_HIP(launch_copy_f64(c->stream, at<double>(c, p.off_Kp), (int64_t)p.nb * nao * nao, out), "copy");
+  return DF_OK;
+}
+
+int df_block_errors(df_ctx* c, int64_t naux, int64_t nao, int64_t nocc, double occ,
+                    const double* kref, double kfro, double* err) {
+  clear_stale_error();
+  const int rc = check_shape(c, DF_DENSE, naux, nao, nocc);
+  if (rc) return rc;
+  if (!kref || !err) return fail(c, DF_EINVAL, "null pointer");
+  if (!(kfro > 0.0) || isinf(kfro)) return fail(c, DF_EINVAL, "kfro must be positive and finite");
+  if (c->blk_s.empty()) return fail(c, DF_EINVAL, "block partials exist only with block precision set");
+  const Plan p = make_plan(c, naux, nao, nocc);
+  if (!c->ws || c->ws_bytes < p.total) return fail(c, DF_EWORKSPACE, "workspace too small");
+  const int64_t nn = nao * nao;
+  for (int b = 0; b < p.nb; ++b)
+    DF_HIP(launch_block_err(c->stream, at<double>(c, p.off_Kp) + b * nn, kref + b * nn, (int)nao,
+                            fabs(occ) / kfro, err + b),
+           "block_err");
+  return DF_OK;
+}
+
+int df_spot_check(df_ctx* c, const double* B, int64_t naux, int64_t nao, const double* C,
+                  int64_t nocc, double occ, double kfro, const int32_t* host_blocks, int nsample,
+                  double* err) {
+  clear_stale_error();
+  const int rc = check_shape(c, DF_DENSE, naux, nao, nocc);
+  if (rc) return rc;
+  if (!B || !C || !host_blocks || !err || nsample < 1) return fail(c, DF_EINVAL, "bad arguments");
+  if (!(kfro > 0.0) || isinf(kfro)) return fail(c, DF_EINVAL, "kfro must be positive and finite");
+  if (c->blk_s.empty()) return fail(c, DF_EINVAL, "block partials exist only with block precision set");
+  const Plan p = make_plan(c, naux, nao, nocc);
+  if (!c->ws || c->ws_bytes < p.total) return fail(c, DF_EWORKSPACE, "workspace too small");
+  for (int i = 0; i < nsample; ++i)
+    if (host_blocks[i] < 0 || host_blocks[i] >= p.nb) return fail(c, DF_EINVAL, "block index out of range");
+  hipStream_t st = c->stream;
+  const int64_t nn = nao * nao;
+  double* Xs = at<double>(c, p.off_Xs);
+  double* Ks = at<double>(c, p.off_Ks);
+  unsigned long long* xm = at<unsigned long long>(c, p.off_xsmax);
+  for (int i = 0; i < nsample; ++i) {
+    const int b = host_blocks[i];
+    const int64_t P0 = (int64_t)b * p.pblk;
+    const int64_t P1 = std::min<int64_t>(P0 + p.pblk, naux);
+    DF_HIP(launch_fill_u64(st, xm, nao, 0ull), "fill");
+    DF_HIP(launch_x_fp64(st, B + P0 * nn, P1 - P0, (int)nao, C, (int)nocc, Xs, 1, xm, p.pblk,
+                         nullptr, nullptr),
+           "x_fp64");
+    DF_HIP(launch_k_fp64(st, Xs, P1 - P0, (int)nao, (int)nocc, p.pblk, 1, 1, Ks), "k_fp64");
+    DF_HIP(launch_block_err(st, at<double>(c, p.off_Kp) + b * nn, Ks, (int)nao, fabs(occ) / kfro,
+                            err + i),
+           "block_err");
+  }
+  return DF_OK;
+}
+
+int df_screen(df_ctx* c, double* B, int64_t naux, int64_t nao, int blk, double tau, uint8_t* mask,
+              uint64_t* chunks, double* norms) {
+  clear_stale_error();
+  const int rc = check_shape(c, DF_DENSE, naux, nao, 1);
+  if (rc) return rc;
+  if (!B || !mask || !chunks) return fail(c, DF_EINVAL, "null pointer");
+  if (blk < 1 || blk > 64 || 64 % blk) return fail(c, DF_EINVAL, "blk must divide 64");
+  if (nao > 4096) return fail(c, DF_EINVAL, "screening supports nao <= 4096");
+  if (!(tau >= 0.0) || isinf(tau)) return fail(c, DF_EINVAL, "tau must be finite and >= 0");
+  const int64_t nblk = (nao + blk - 1) / blk;
+  const size_t per_split = (size_t)nblk * nao * 8;
+  double* part;
+  int nsplit;
+  if (per_split <= kAuxBytes) {
+    part = reinterpret_cast<double*>(c->aux);
+    nsplit = (int)std::min<int64_t>({(int64_t)(kAuxBytes / per_split), 64,
+                                     std::max<int64_t>(1, (1024 + nblk - 1) / nblk), naux});
+  } else {
+    if (!c->ws || c->ws_bytes < per_split)
+      return fail(c, DF_EWORKSPACE, "screening needs a workspace of nblk * nao * 8 bytes");
+    part = reinterpret_cast<double*>(c->ws);
+    nsplit = 1;
+  }
+  DF_HIP(launch_screen(c->stream, B, naux, (int)nao, blk, tau, nsplit, part, norms, mask,
+                       reinterpret_cast<unsigned long long*>(chunks)),
+         "screen");
+  return DF_OK;
+}
+
+int df_set_screening(df_ctx* c, const uint8_t* mask, const uint64_t* chunks, int blk, int64_t nao) {
+  if (!c) return DF_EINVAL;
+  if (!mask || !chunks) {
+    c->scr_mask = nullptr;
+    c->scr_chunks = nullptr;
+    c->scr_nao = 0;
+    return DF_OK;
+  }
+  if (blk < 1 || blk > 64 || 64 % blk) return fail(c, DF_EINVAL, "blk must divide 64");
+  if (nao < 1 || nao > 4096) return fail(c, DF_EINVAL, "screening supports nao <= 4096");
+  c->scr_mask = mask;
+  c->scr_chunks = reinterpret_cast<const unsigned long long*>(chunks);
+  c->scr_blk = blk;
+  c->scr_nao = nao;
+  return DF_OK;
+}
+
 int df_timing_begin(df_ctx* c, int max_calls) {
+  clear_stale_error();
   if (!c) return DF_EINVAL;
   if (max_calls < 1 || max_calls > 100000) return fail(c, DF_EINVAL, "max_calls must be 1..100000");
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -655,6 +917,7 @@ int df_timing_end(df_ctx* c, double* ms_sum, int* ncalls) {
 }
 
 int df_metric_cholesky(df_ctx* c, double* W, int64_t n) {
+  clear_stale_error();
   if (!c) return DF_EINVAL;
   if (!W || n < 1 || n > 65536) return fail(c, DF_EINVAL, "bad W or n");
   DF_HIP(launch_cholesky(c->stream, W, n, c->status), "cholesky");
@@ -662,6 +925,7 @@ int df_metric_cholesky(df_ctx* c, double* W, int64_t n) {
 }
 
 int df_whiten(df_ctx* c, const double* L, int64_t naux, const double* T, int64_t ncols, double* B) {
+  clear_stale_error();
   if (!c) return DF_EINVAL;
   if (!L || !T || !B || naux < 1 || naux > 65536 || ncols < 1) return fail(c, DF_EINVAL, "bad arguments");
   if (B == T) return fail(c, DF_EINVAL, "B must not alias T");
@@ -674,6 +938,7 @@ int df_whiten(df_ctx* c, const double* L, int64_t naux, const double* T, int64_t
 }
 
 int df_density(df_ctx* c, const double* C, int64_t nao, int64_t nocc, double occ, double* D) {
+  clear_stale_error();
   if (!c) return DF_EINVAL;
   if (!C || !D || nao < 1 || nocc < 1 || nocc > nao) return fail(c, DF_EINVAL, "bad arguments");
   DF_HIP(launch_density(c->stream, C, nao, nocc, occ, D), "density");
@@ -703,7 +968,57 @@ int df_rule_slices(int level, int fp64_below_level) {
   return (m + 1 + 7) / 8;
 }
 
+int df_controller_allocate(const float* pred, int64_t nblocks, int s_ref, double slack,
+                           int32_t* s_out) {
+  if (!pred || !s_out || nblocks < 1 || s_ref < 0 || s_ref > kMaxSlices || !(slack > 0.0))
+    return DF_EINVAL;
+  if (s_ref == 0) {
+    for (int64_t b = 0; b < nblocks; ++b) s_out[b] = 0;
+    return DF_OK;
+  }
+  // predicted errors, made non-increasing in s
+  std::vector<double> err((size_t)nblocks * kMaxSlices);
+  for (int64_t b = 0; b < nblocks; ++b) {
+    double e = pow(10.0, (double)pred[b * kMaxSlices]);
+    for (int k = 0; k < kMaxSlices; ++k) {
+      e = std::min(e, pow(10.0, (double)pred[b * kMaxSlices + k]));
+      err[b * kMaxSlices + k] = e;
+    }
+  }
+  auto E = [&](int64_t b, int s) { return err[b * kMaxSlices + s - 1]; };
+  double budget = 0.0;
+  for (int64_t b = 0; b < nblocks; ++b) {
+    budget += E(b, s_ref);
+    s_out[b] = 1;
+  }
+  budget *= slack;
+  for (;;) {
+    double total = 0.0;  // the predicted total, in block order
+    for (int64_t b = 0; b < nblocks; ++b) total += E(b, s_out[b]);
+    if (!(total > budget)) break;
+    int64_t best = -1;
+    int best_to = 0;
+    double gain = 0.0;
+    for (int64_t b = 0; b < nblocks; ++b) {
+      const int sb = s_out[b];
+      int to = sb + 1;
+      while (to <= kMaxSlices && !(E(b, to) < E(b, sb))) ++to;
+      if (to > kMaxSlices) continue;
+      const double g = (E(b, sb) - E(b, to)) / (double)(to * (to + 1) / 2 - sb * (sb + 1) / 2);
+      if (best < 0 || g > gain) {
+        best = b;
+        gain = g;
+        best_to = to;
+      }
+    }
+    if (best < 0) break;
+    s_out[best] = best_to;
+  }
+  return DF_OK;
+}
+
 int df_get_status(df_ctx* c) {
+  clear_stale_error();
   if (!c) return DF_EINVAL;
   int h = 0;
   hipError_t e = hipMemcpyAsync(&h, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
@@ -720,6 +1035,7 @@ const char* df_last_error(const df_ctx* c) { return c ? c->err.c_str() : "null c
 
 int df_debug_slice_gemm_i32(df_ctx* c, const int8_t* a_dig, const int8_t* b_dig, int64_t m,
                             int64_t n, int64_t k, int s, int32_t* partials) {
+  clear_stale_error();
   if (!c) return DF_EINVAL;
   if (!a_dig || !b_dig || !partials) return fail(c, DF_EINVAL, "null pointer");
   if (m < 1 || n < 1 || k < 1 || s < 1 || s > kMaxSlices) return fail(c, DF_EINVAL, "bad shape");

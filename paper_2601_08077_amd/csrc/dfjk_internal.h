@@ -66,6 +66,42 @@ __host__ __device__ inline double kappa_of(int s, int64_t k) {
   return 2.0 * eps + eps * eps + dropped + rounding;
 }
 
+// Set bits of a chunk mask: the first one, and the first one above c (-1: none).
+__device__ __forceinline__ int first_bit(unsigned long long m) {
+  return m ? __ffsll((unsigned long long)m) - 1 : -1;
+}
+__device__ __forceinline__ int next_bit(unsigned long long m, int c) {
+  const unsigned long long r = c >= 63 ? 0ull : (m >> (c + 1)) << (c + 1);
+  return r ? __ffsll((unsigned long long)r) - 1 : -1;
+}
+
+// Union over the 64 rows m0 .. m0 + 63 (rows < M; row r is basis row r % nao)
+// of the per-row masks of 64-wide nu chunks that meet a kept block of the
+// screened B, folded to 128-wide chunks when KSUB == 2.  Every thread of the
+// workgroup must call it (it synchronises); wave 0 does the reduction.
+template <int KSUB>
+__device__ __forceinline__ unsigned long long tile_chunks(const unsigned long long* cmask,
+                                                          int64_t m0, int64_t M, int nao, int w,
+                                                          int l) {
+  __shared__ unsigned long long tmask;
+  if (w == 0) {
+    const int64_t row = m0 + l;
+    unsigned long long m = row < M ? cmask[row % nao] : 0ull;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m |= __shfl_xor(m, off);
+    if (l == 0) tmask = m;
+  }
+  __syncthreads();
+  unsigned long long live = tmask;
+  if (KSUB == 2) {
+    unsigned long long f = 0;
+    for (int c = 0; c < 32; ++c)
+      if ((live >> (2 * c)) & 3ull) f |= 1ull << c;
+    live = f;
+  }
+  return live;
+}
+
 __device__ __forceinline__ double abs_max_bits_to_double(unsigned long long b) {
   return __longlong_as_double((long long)b);
 }
@@ -98,7 +134,8 @@ hipError_t launch_fill_i32(hipStream_t st, int* p, int64_t n, int v);
 hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, int nao,
                          const int32_t* b_exp, const int8_t* dC, int ncp, int kp,
                          const int32_t* f_col, int nocc, double* X, int xlayout,
-                         unsigned long long* xmax, int pblk, const double* D, double* rowdot);
+                         unsigned long long* xmax, int pblk, const double* D, double* rowdot,
+                         const unsigned long long* cmask = nullptr);
 // X in the blocked layout.
 hipError_t launch_slice_x(hipStream_t st, int s, const double* Xb, int64_t naux, int nao,
                           int nocc, int pblk, int nao_pad, int kbp,
@@ -112,7 +149,8 @@ hipError_t launch_debug_pairs(hipStream_t st, int s, const int8_t* a_dig, const 
 // fp64_gemm.hip
 hipError_t launch_x_fp64(hipStream_t st, const double* B, int64_t naux, int nao,
                          const double* C, int nocc, double* X, int xlayout,
-                         unsigned long long* xmax, int pblk, const double* D, double* rowdot);
+                         unsigned long long* xmax, int pblk, const double* D, double* rowdot,
+                         const unsigned long long* cmask = nullptr);
 // X in the blocked layout.
 hipError_t launch_k_fp64(hipStream_t st, const double* Xb, int64_t naux, int nao, int nocc,
                          int pblk, int nb, int groups, double* Kp);
@@ -133,8 +171,10 @@ hipError_t launch_rho(hipStream_t st, const double* B, int64_t naux, int nao, co
 // rho_P = sum_mu rowdot[P*nao + mu] (fixed order).
 hipError_t launch_rho_reduce(hipStream_t st, const double* rowdot, int64_t naux, int nao,
                              double* rho);
+// With smask ([nblk][nblk] kept shell blocks of size blk), dropped blocks are
+// not read (they are zero in the screened B).
 hipError_t launch_j(hipStream_t st, const double* B, int64_t naux, int nao, const double* rho,
-                    int jsplit, double* Jp, double* J);
+                    int jsplit, double* Jp, double* J, const uint8_t* smask = nullptr, int blk = 8);
 hipError_t launch_k_reduce(hipStream_t st, const double* Kp, int groups, int nao, double occ,
                            double* K);
 // scratch: 2 * 256 doubles.
@@ -167,5 +207,36 @@ hipError_t launch_j_dig(hipStream_t st, int s, const int8_t* Bd, int64_t bplane,
                         const double* rho, const double* drho, const int32_t* b_exp, int64_t naux,
                         int nao, int naux_pad, int nsplit, double kap_j, int32_t* h, int8_t* wd,
                         unsigned long long* Sj, unsigned long long* jbound, double* J);
+
+// screen.hip: shell-block norms over all P (part: nsplit * nblk * nao doubles),
+// mask (keep iff norm >= tau), zeroing of the dropped blocks of B in place,
+// per-row chunk masks (64-wide nu chunks, nao <= 4096); norms may be null.
+hipError_t launch_screen(hipStream_t st, double* B, int64_t naux, int nao, int blk, double tau,
+                         int nsplit, double* part, double* norms, uint8_t* mask,
+                         unsigned long long* chunks);
+
+// controller.hip (the per-block slice controller)
+struct CtlScalars {  // host scalars of one iteration, passed by value
+  double iteration, n_iter, de_rel, target, nao, naux, nocc, plain_s;
+};
+int mlp_nparam();
+// out[seg] = (max |A - A2|, sum (A - A2)^2) over segments of seglen elements (A2 may be null);
+// in the last segment only the first last_valid of every rowlen elements count;
+// partial: nseg * nsplit * 2 doubles.
+hipError_t launch_seg_stats(hipStream_t st, const double* A, const double* A2, int64_t n,
+                            int64_t seglen, int64_t rowlen, int64_t last_valid, double* partial,
+                            int nsplit, double* out);
+hipError_t launch_features(hipStream_t st, const double* bstats, const double* xstats,
+                           const double* dstat, const double* cstat, const double* kstat,
+                           const CtlScalars& sc, int nb, float* feat);
+hipError_t launch_mlp_forward(hipStream_t st, const float* prm, const float* x, int64_t n, float* y);
+// gpart: ceil(n / 32) * (nparam + 1) floats; cnt: 1 float.
+hipError_t launch_mlp_train(hipStream_t st, float* prm, float* m1, float* m2, int64_t step,
+                            const float* x, const float* t, const float* mask, const int32_t* idx,
+                            int64_t n, float lr, float* gpart, float* cnt, float* loss);
+hipError_t launch_choose(hipStream_t st, const float* pred, int64_t n, double target, int32_t* s);
+hipError_t launch_block_err(hipStream_t st, const double* Kp, const double* Kref, int nao,
+                            double scale, double* err);
+hipError_t launch_copy_f64(hipStream_t st, const double* a, int64_t n, double* b);
 
 }  // namespace dfjk

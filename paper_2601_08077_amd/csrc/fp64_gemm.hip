@@ -23,7 +23,8 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
                                                 double* __restrict__ X, int xlayout,
                                                 unsigned long long* __restrict__ xmax, int nao,
                                                 int pblk, const double* __restrict__ D,
-                                                double* __restrict__ rowdot) {
+                                                double* __restrict__ rowdot,
+                                                const unsigned long long* __restrict__ cmask) {
   constexpr int NT = 16 * NF;
   __shared__ double As[2][64][17];
   __shared__ double Cs[2][16][NT + 1];
@@ -64,9 +65,20 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
       vc[j] = (kk < K && col < nocc) ? C[(int64_t)kk * nocc + col] : 0.0;
     }
   };
-  load(0);
+  // Screened B: only the 64-wide nu chunks that meet a kept block in some row
+  // of this tile are visited, 16 k at a time.
+  const unsigned long long live = cmask ? tile_chunks<1>(cmask, m0, M, nao, w, l) : 0ull;
+  int k0 = cmask ? 64 * first_bit(live) : 0;
+  if (k0 < 0 || k0 >= K) k0 = -1;
+  if (k0 >= 0) load(k0);
   int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += 16, buf ^= 1) {
+  while (k0 >= 0) {
+    int kn = k0 + 16;
+    if (cmask && kn % 64 == 0) {
+      const int c = next_bit(live, k0 / 64);
+      kn = c >= 0 ? 64 * c : -1;
+    }
+    if (kn >= K) kn = -1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) As[buf][lr][lk + j] = va[j];
 #pragma unroll
@@ -83,7 +95,7 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
       }
     }
     __syncthreads();
-    if (k0 + 16 < K) load(k0 + 16);
+    if (kn >= 0) load(kn);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const double a = As[buf][w * 16 + (l & 15)][kk * 4 + (l >> 4)];
@@ -91,6 +103,8 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
       for (int f = 0; f < NF; ++f)
         acc[f] = mfma_f64(a, Cs[buf][kk * 4 + (l >> 4)][f * 16 + (l & 15)], acc[f]);
     }
+    k0 = kn;
+    buf ^= 1;
   }
 
   if (rowdot) {
@@ -230,19 +244,20 @@ __global__ void k_xmax_to_exp(const unsigned long long* __restrict__ xmax, int64
 
 hipError_t launch_x_fp64(hipStream_t st, const double* B, int64_t naux, int nao,
                          const double* C, int nocc, double* X, int xlayout,
-                         unsigned long long* xmax, int pblk, const double* D, double* rowdot) {
+                         unsigned long long* xmax, int pblk, const double* D, double* rowdot,
+                         const unsigned long long* cmask) {
   const int64_t M = naux * nao;
   if (M <= 0 || nocc <= 0) return hipSuccess;
   const unsigned gx = (unsigned)((M + 63) / 64);
   if (nocc > 64) {
     hipLaunchKernelGGL((k_x_fp64<6>), dim3(gx, (nocc + 95) / 96), dim3(256), 0, st, B, M, nao, C,
-                       nocc, X, xlayout, xmax, nao, pblk, D, rowdot);
+                       nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
   } else if (nocc > 32) {
     hipLaunchKernelGGL((k_x_fp64<4>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X,
-                       xlayout, xmax, nao, pblk, D, rowdot);
+                       xlayout, xmax, nao, pblk, D, rowdot, cmask);
   } else {
     hipLaunchKernelGGL((k_x_fp64<2>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X,
-                       xlayout, xmax, nao, pblk, D, rowdot);
+                       xlayout, xmax, nao, pblk, D, rowdot, cmask);
   }
   return hipGetLastError();
 }

@@ -44,7 +44,8 @@ __global__ __launch_bounds__(512) void k_x_int8(
     const double* __restrict__ B, int64_t M, int K, const int32_t* __restrict__ b_exp,
     const int8_t* __restrict__ dC, int ncp, int kp, const int32_t* __restrict__ f_col, int nocc,
     double* __restrict__ X, int xlayout, unsigned long long* __restrict__ xmax, int nao, int pblk,
-    const double* __restrict__ D, double* __restrict__ rowdot) {
+    const double* __restrict__ D, double* __restrict__ rowdot,
+    const unsigned long long* __restrict__ cmask) {
   constexpr int NT = 16 * NF, NFW = NF / 2;
   constexpr int KC = 64 * KSUB, ROW = KC + 16;  // LDS rows: KC k bytes + 16 B pad
   constexpr int CUNITS = S * NT * 4 * KSUB;     // 16-byte units of C digits per chunk
@@ -77,6 +78,9 @@ __global__ __launch_bounds__(512) void k_x_int8(
   const double* drow = (want_rd ? D : B) + (aok ? (arow % nao) : 0) * (int64_t)K + 2 * q + 32 * half;
   const int nch = (K + KC - 1) / KC;
   int8_t* adst = &As[0][wrow * 16 + r16][q * 16 + half * 8];
+  // Screened B: only the KC-wide nu chunks that meet a kept block in some row
+  // of this tile are visited (the rest of the tile is zero).
+  const unsigned long long live = cmask ? tile_chunks<KSUB>(cmask, m0, M, nao, w, l) : 0ull;
 
   const int8_t* csrc[CPER];
   int cdst[CPER];
@@ -131,8 +135,10 @@ __global__ __launch_bounds__(512) void k_x_int8(
     }                                                                                      \
   }
 
-  DFJK_X_LOAD(0)
-  for (int c = 0; c < nch; ++c) {
+  int c = cmask ? first_bit(live) : (nch > 0 ? 0 : -1);
+  if (c >= 0) DFJK_X_LOAD(c)
+  while (c >= 0) {
+    const int cn = cmask ? next_bit(live, c) : (c + 1 < nch ? c + 1 : -1);
     // slice this lane's values into S digit planes (8 bytes per sub-chunk)
     uint32_t lo[KSUB][S], hi[KSUB][S];
     {
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
     for (int i = 0; i < CPER; ++i)
       if (t + 512 * i < CUNITS) *reinterpret_cast<i32x4*>(&Cs[0][0][0] + cdst[i]) = cpre[i];
     __syncthreads();  // A and C digits of chunk c are in LDS
-    if (c + 1 < nch) DFJK_X_LOAD(c + 1)
+    if (cn >= 0) DFJK_X_LOAD(cn)
 #pragma unroll
     for (int sub = 0; sub < KSUB; ++sub) {
       i32x4 af[S];
@@ -184,6 +190,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
                 __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a + b][f], 0, 0, 0);
       }
     }
+    c = cn;
   }
 #undef DFJK_X_LOAD
 
@@ -471,17 +478,17 @@ template <int S, bool FULLK, int KSUB>
 hipError_t launch_x_sk(hipStream_t st, const double* B, int64_t M, int nao, const int32_t* b_exp,
                        const int8_t* dC, int ncp, int kp, const int32_t* f_col, int nocc,
                        double* X, int xlayout, unsigned long long* xmax, int pblk, const double* D,
-                       double* rowdot) {
+                       double* rowdot, const unsigned long long* cmask) {
   const unsigned gx = (unsigned)((M + 63) / 64);
   if (ncp % 96 == 0) {
     hipLaunchKernelGGL((k_x_int8<S, 6, FULLK, KSUB>), dim3(gx, ncp / 96), dim3(512), 0, st, B, M,
-                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot);
+                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
   } else if (ncp % 64 == 0) {
     hipLaunchKernelGGL((k_x_int8<S, 4, FULLK, KSUB>), dim3(gx, ncp / 64), dim3(512), 0, st, B, M,
-                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot);
+                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
   } else {
     hipLaunchKernelGGL((k_x_int8<S, 2, FULLK, KSUB>), dim3(gx, ncp / 32), dim3(512), 0, st, B, M,
-                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot);
+                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
   }
   return hipGetLastError();
 }
@@ -492,15 +499,15 @@ template <int S>
 hipError_t launch_x_s(hipStream_t st, const double* B, int64_t M, int nao, const int32_t* b_exp,
                       const int8_t* dC, int ncp, int kp, const int32_t* f_col, int nocc,
                       double* X, int xlayout, unsigned long long* xmax, int pblk, const double* D,
-                      double* rowdot) {
+                      double* rowdot, const unsigned long long* cmask) {
   if (S <= 5 && nao % 128 == 0)
     return launch_x_sk<S, true, (S <= 5 ? 2 : 1)>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X,
-                                                   xlayout, xmax, pblk, D, rowdot);
+                                                   xlayout, xmax, pblk, D, rowdot, cmask);
   if (nao % 64 == 0)
     return launch_x_sk<S, true, 1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax,
-                                   pblk, D, rowdot);
+                                   pblk, D, rowdot, cmask);
   return launch_x_sk<S, false, 1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax,
-                                  pblk, D, rowdot);
+                                  pblk, D, rowdot, cmask);
 }
 
 }  // namespace
@@ -508,18 +515,19 @@ hipError_t launch_x_s(hipStream_t st, const double* B, int64_t M, int nao, const
 hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, int nao,
                          const int32_t* b_exp, const int8_t* dC, int ncp, int kp,
                          const int32_t* f_col, int nocc, double* X, int xlayout,
-                         unsigned long long* xmax, int pblk, const double* D, double* rowdot) {
+                         unsigned long long* xmax, int pblk, const double* D, double* rowdot,
+                         const unsigned long long* cmask) {
   const int64_t M = naux * nao;
   if (M <= 0 || nocc <= 0) return hipSuccess;
   switch (s) {
-    case 1: return launch_x_s<1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
-    case 2: return launch_x_s<2>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
-    case 3: return launch_x_s<3>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
-    case 4: return launch_x_s<4>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
-    case 5: return launch_x_s<5>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
-    case 6: return launch_x_s<6>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
-    case 7: return launch_x_s<7>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
-    case 8: return launch_x_s<8>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot);
+    case 1: return launch_x_s<1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask);
+    case 2: return launch_x_s<2>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask);
+    case 3: return launch_x_s<3>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask);
+    case 4: return launch_x_s<4>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask);
+    case 5: return launch_x_s<5>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask);
+    case 6: return launch_x_s<6>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask);
+    case 7: return launch_x_s<7>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask);
+    case 8: return launch_x_s<8>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask);
     default: return hipErrorInvalidValue;
   }
 }

@@ -42,43 +42,71 @@ __global__ __launch_bounds__(256) void k_rho(const double* __restrict__ B, int64
   if (t == 0) rho[P] = r;
 }
 
-// J partials (Eq. 4): Jp[split][e] = sum over P of the split of rho_P B[P][e],
-// two consecutive elements per thread.
-__global__ __launch_bounds__(256) void k_j(const double* __restrict__ B, int64_t naux, int64_t nn,
-                                           const double* __restrict__ rho, int jsplit,
-                                           double* __restrict__ out) {
-  const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
+// J partials (Eq. 4) over the lower triangle (J and every B_P are symmetric):
+// Jp[split][mu][nu] = sum over P of the split (ascending) of rho_P B[P][mu][nu],
+// nu <= mu.  Workgroup w takes rows w and nao - 1 - w, nao + 1 elements in
+// all, so every workgroup streams the same number of bytes; thread t owns
+// elements t, t + 256, ... of the two rows, concatenated.
+template <int EPT>
+__global__ __launch_bounds__(256) void k_j_tri(const double* __restrict__ B, int64_t naux, int nao,
+                                               const double* __restrict__ rho, int jsplit,
+                                               double* __restrict__ out, int mirror,
+                                               const uint8_t* __restrict__ smask, int blk) {
+  const int w = blockIdx.x;
+  const int mu0 = w, mu1 = nao - 1 - w;
+  const int n0 = mu0 + 1;
+  const int ntot = mu1 > mu0 ? n0 + mu1 + 1 : n0;
   const int split = blockIdx.y;
   const int64_t p_lo = (int64_t)split * naux / jsplit, p_hi = (int64_t)(split + 1) * naux / jsplit;
-  if (e0 >= nn) return;
-  double a0 = 0.0, a1 = 0.0;
-  if (e0 + 1 < nn && (nn & 1) == 0) {
-    for (int64_t P = p_lo; P < p_hi; ++P) {
-      const double2 b = *reinterpret_cast<const double2*>(B + P * nn + e0);
-      const double r = rho[P];
-      a0 = fma(r, b.x, a0);
-      a1 = fma(r, b.y, a1);
+  const int64_t nn = (int64_t)nao * nao;
+  for (int base = 0; base < ntot; base += 256 * EPT) {
+    int64_t off[EPT];
+    bool ok[EPT], rd[EPT];
+    const int nblk = (nao + blk - 1) / blk;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int idx = base + threadIdx.x + 256 * j;
+      ok[j] = idx < ntot;
+      const int mu = idx < n0 ? mu0 : mu1;
+      const int nu = idx < n0 ? idx : idx - n0;
+      off[j] = ok[j] ? (int64_t)mu * nao + nu : 0;
+      // a dropped shell block of the screened B is zero: its sum is 0
+      rd[j] = ok[j] && (!smask || smask[(mu / blk) * nblk + nu / blk]);
     }
-    out[split * nn + e0] = a0;
-    out[split * nn + e0 + 1] = a1;
-  } else {
+    double a[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) a[j] = 0.0;
     for (int64_t P = p_lo; P < p_hi; ++P) {
       const double r = rho[P];
-      a0 = fma(r, B[P * nn + e0], a0);
-      if (e0 + 1 < nn) a1 = fma(r, B[P * nn + e0 + 1], a1);
+      const double* bp = B + P * nn;
+#pragma unroll
+      for (int j = 0; j < EPT; ++j)
+        if (rd[j]) a[j] = fma(r, bp[off[j]], a[j]);
     }
-    out[split * nn + e0] = a0;
-    if (e0 + 1 < nn) out[split * nn + e0 + 1] = a1;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      if (!ok[j]) continue;
+      out[split * nn + off[j]] = a[j];
+      if (mirror) {
+        const int64_t mu = off[j] / nao, nu = off[j] - mu * nao;
+        out[nu * nao + mu] = a[j];
+      }
+    }
   }
 }
 
-__global__ void k_sum_splits(const double* __restrict__ Jp, int jsplit, int64_t nn,
+// J[mu][nu] = J[nu][mu] = sum of the split partials (splits ascending), nu <= mu.
+__global__ void k_sum_splits(const double* __restrict__ Jp, int jsplit, int nao,
                              double* __restrict__ J) {
+  const int64_t nn = (int64_t)nao * nao;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
        e += (int64_t)gridDim.x * blockDim.x) {
+    const int mu = (int)(e / nao), nu = (int)(e - (int64_t)mu * nao);
+    if (nu > mu) continue;
     double v = 0.0;
     for (int s = 0; s < jsplit; ++s) v += Jp[s * nn + e];
     J[e] = v;
+    J[(int64_t)nu * nao + mu] = v;
   }
 }
 
@@ -228,17 +256,17 @@ hipError_t launch_rho(hipStream_t st, const double* B, int64_t naux, int nao, co
 }
 
 hipError_t launch_j(hipStream_t st, const double* B, int64_t naux, int nao, const double* rho,
-                    int jsplit, double* Jp, double* J) {
+                    int jsplit, double* Jp, double* J, const uint8_t* smask, int blk) {
   const int64_t nn = (int64_t)nao * nao;
-  const unsigned gx = (unsigned)((nn + 511) / 512);
+  const dim3 grid((unsigned)((nao + 1) / 2), (unsigned)jsplit);
   if (jsplit <= 1) {
-    hipLaunchKernelGGL(k_j, dim3(gx, 1), dim3(256), 0, st, B, naux, nn, rho, 1, J);
+    hipLaunchKernelGGL((k_j_tri<4>), grid, dim3(256), 0, st, B, naux, nao, rho, 1, J, 1, smask, blk);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_j, dim3(gx, (unsigned)jsplit), dim3(256), 0, st, B, naux, nn, rho, jsplit, Jp);
+  hipLaunchKernelGGL((k_j_tri<4>), grid, dim3(256), 0, st, B, naux, nao, rho, jsplit, Jp, 0, smask, blk);
   int64_t g = (nn + 255) / 256;
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)g), dim3(256), 0, st, Jp, jsplit, nn, J);
+  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)g), dim3(256), 0, st, Jp, jsplit, nao, J);
   return hipGetLastError();
 }
 
