@@ -196,6 +196,51 @@ int df_screen(df_ctx* ctx, double* B, int64_t naux, int64_t nao, int blk, double
 int df_set_screening(df_ctx* ctx, const uint8_t* mask, const uint64_t* chunks, int blk,
                      int64_t nao);
 
+/* Autotuner of the launch shapes of df_build_jk for one shape at the context
+ * precision and aux block size: the number of K partial groups (1, 2, 4, ...,
+ * min(nblocks, 64), plus the default) and, for s <= 5 with nao % 128 == 0,
+ * the k depth staged per X step (64 or 128).  Each candidate that fits the
+ * current workspace runs 1 + reps full builds on the given arguments (timed
+ * with HIP events; the call synchronises); the fastest is kept in the
+ * context and used by every later df_build_jk / df_workspace_size of that
+ * shape, precision and pblk unless df_set_k_groups fixes the groups.
+ * best_groups / best_ksub / best_ms (host, may be NULL) receive the choice. */
+int df_autotune(df_ctx* ctx, const double* B, const int32_t* b_exp, int64_t naux, int64_t nao,
+                const double* C, int64_t nocc, double occ, const double* D, double* J, double* K,
+                double* energies, double* err_bound, int reps, int* best_groups, int* best_ksub,
+                double* best_ms);
+
+/* Batched build of independent, uneven instances.  Each df_problem is one
+ * df_build_jk call (dense B; b_exp may be NULL; its own slice count and
+ * optional screening masks from df_screen, NULL = dense) with its own
+ * outputs.  Instances are ordered by estimated cost, largest first, and
+ * dealt onto `streams` (1..4) streams, each to the least-loaded one; with
+ * streams > 1 the context creates worker streams (default priority) that
+ * start after the work already queued on its stream and that its stream
+ * waits for, so the call stays asynchronous and ordered like one build.
+ * Every instance uses the autotuned shapes of df_autotune when present.
+ * Workspace: df_batched_workspace_size (the sum over streams of the largest
+ * instance plan on each).  The context's per-block precision must be unset. */
+typedef struct df_problem {
+  const double* B;
+  const int32_t* b_exp;
+  int64_t naux, nao, nocc;
+  const double* C;
+  const double* D;
+  double occ;
+  int slices;
+  const uint8_t* screen_mask;
+  const uint64_t* screen_chunks;
+  int screen_blk;
+  double* J;
+  double* K;
+  double* energies;
+  double* err_bound;
+} df_problem;
+int df_batched_workspace_size(df_ctx* ctx, int n, const df_problem* probs, int streams,
+                              size_t* bytes);
+int df_build_jk_batched(df_ctx* ctx, int n, const df_problem* probs, int streams);
+
 /* Metric Cholesky (Sec. 2.1, Eq. 2): W [n][n] symmetric positive definite is
  * overwritten in place by L (lower triangle; the upper triangle is set to 0)
  * with L L^T = W, in FP64.  A non-positive pivot sets the DF_ENOTSPD device

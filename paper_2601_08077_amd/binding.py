@@ -19,6 +19,15 @@ _c_void_p = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _int = ctypes.c_int
 
+
+class DFProblem(ctypes.Structure):
+    """struct df_problem of dfjk.h (one instance of the batched build)."""
+    _fields_ = [("B", _c_void_p), ("b_exp", _c_void_p), ("naux", _i64), ("nao", _i64),
+                ("nocc", _i64), ("C", _c_void_p), ("D", _c_void_p), ("occ", ctypes.c_double),
+                ("slices", _int), ("screen_mask", _c_void_p), ("screen_chunks", _c_void_p),
+                ("screen_blk", _int), ("J", _c_void_p), ("K", _c_void_p),
+                ("energies", _c_void_p), ("err_bound", _c_void_p)]
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "df_create": (_int, [ctypes.POINTER(_c_void_p), _c_void_p]),
@@ -63,6 +72,13 @@ SIGNATURES = {
     "df_screen": (_int, [_c_void_p, _c_void_p, _i64, _i64, _int, ctypes.c_double, _c_void_p,
                          _c_void_p, _c_void_p]),
     "df_set_screening": (_int, [_c_void_p, _c_void_p, _c_void_p, _int, _i64]),
+    "df_autotune": (_int, [_c_void_p, _c_void_p, _c_void_p, _i64, _i64, _c_void_p, _i64,
+                           ctypes.c_double, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                           _int, ctypes.POINTER(_int), ctypes.POINTER(_int),
+                           ctypes.POINTER(ctypes.c_double)]),
+    "df_batched_workspace_size": (_int, [_c_void_p, _int, ctypes.POINTER(DFProblem), _int,
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "df_build_jk_batched": (_int, [_c_void_p, _int, ctypes.POINTER(DFProblem), _int]),
     "df_get_status": (_int, [_c_void_p]),
     "df_last_error": (ctypes.c_char_p, [_c_void_p]),
     "df_metric_cholesky": (_int, [_c_void_p, _c_void_p, _i64]),
@@ -278,6 +294,41 @@ class Context:
     def df_set_screening(self, mask, chunks, blk, nao):
         self._check(self.lib.df_set_screening(self.h, _ptr(mask), _ptr(chunks), int(blk), int(nao)),
                     "df_set_screening")
+
+    def df_autotune(self, B, b_exp, C, occ, D, J, K, energies, err_bound, reps=3):
+        """Returns (groups, ksub, ms) of the fastest launch shape, kept in the context."""
+        naux, nao = B.shape[0], B.shape[1]
+        g, k, ms = _int(), _int(), ctypes.c_double()
+        self._check(self.lib.df_autotune(self.h, _ptr(B), _ptr(b_exp), naux, nao, _ptr(C),
+                                         C.shape[1], float(occ), _ptr(D), _ptr(J), _ptr(K),
+                                         _ptr(energies), _ptr(err_bound), int(reps),
+                                         ctypes.byref(g), ctypes.byref(k), ctypes.byref(ms)),
+                    "df_autotune")
+        return g.value, k.value, ms.value
+
+    @staticmethod
+    def make_problem(B, C, D, J, K, energies, err_bound, slices, occ=2.0, b_exp=None,
+                     screen_mask=None, screen_chunks=None, screen_blk=8):
+        naux, nao = B.shape[0], B.shape[1]
+        return DFProblem(B.data_ptr(), 0 if b_exp is None else b_exp.data_ptr(), naux, nao,
+                         C.shape[1], C.data_ptr(), D.data_ptr(), float(occ), int(slices),
+                         0 if screen_mask is None else screen_mask.data_ptr(),
+                         0 if screen_chunks is None else screen_chunks.data_ptr(),
+                         int(screen_blk), J.data_ptr(), K.data_ptr(), energies.data_ptr(),
+                         err_bound.data_ptr())
+
+    def df_batched_workspace_size(self, problems, streams):
+        arr = (DFProblem * len(problems))(*problems)
+        n = ctypes.c_size_t()
+        self._check(self.lib.df_batched_workspace_size(self.h, len(problems), arr, int(streams),
+                                                       ctypes.byref(n)),
+                    "df_batched_workspace_size")
+        return n.value
+
+    def df_build_jk_batched(self, problems, streams):
+        arr = (DFProblem * len(problems))(*problems)
+        self._check(self.lib.df_build_jk_batched(self.h, len(problems), arr, int(streams)),
+                    "df_build_jk_batched")
 
     def df_metric_cholesky(self, W):
         """In place: the lower triangle of W becomes L (L L^T = W), upper set to 0."""

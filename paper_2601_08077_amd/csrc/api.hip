@@ -5,7 +5,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/dfjk.h"
@@ -37,6 +39,13 @@ struct df_ctx {
   const unsigned long long* scr_chunks = nullptr;
   int scr_blk = 8;
   int64_t scr_nao = 0;
+  // autotuned launch shapes per (naux, nao, nocc, slices, pblk): K groups, X chunk depth
+  std::map<std::tuple<int64_t, int64_t, int64_t, int, int>, std::pair<int, int>> tuned;
+  // worker streams of the batched build (created on first use, default
+  // priority), their join events and the fork event
+  std::vector<hipStream_t> workers;
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
 };
 
 constexpr size_t kAuxBytes = (size_t)8 << 20;
@@ -94,7 +103,12 @@ Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
   const int nt = p.nao_pad / 64;
   const int tiles = nt * (nt + 1) / 2;
   int g = c->k_groups_req;
-  if (g <= 0) g = (int)std::min<int64_t>(std::max<int64_t>(1, (1024 + tiles - 1) / tiles), 64);
+  if (g <= 0) {
+    const auto it = c->tuned.find(std::make_tuple(naux, nao, nocc, c->slices, c->pblk));
+    g = it != c->tuned.end()
+            ? it->second.first
+            : (int)std::min<int64_t>(std::max<int64_t>(1, (1024 + tiles - 1) / tiles), 64);
+  }
   p.groups = std::max(1, std::min(g, p.nb));
   if (!c->blk_s.empty()) p.groups = p.nb;  // per-block precision: one partial per block
   const int64_t nn = nao * nao;
@@ -165,6 +179,12 @@ int check_guard(df_ctx* c, int s, int64_t nao, int64_t nocc) {
 template <class T>
 T* at(df_ctx* c, size_t off) {
   return reinterpret_cast<T*>(c->ws + off);
+}
+
+// Autotuned X chunk depth for this shape at the context precision (0 = default).
+int ksub_for(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
+  const auto it = c->tuned.find(std::make_tuple(naux, nao, nocc, c->slices, c->pblk));
+  return it != c->tuned.end() ? it->second.second : 0;
 }
 
 // Chunk and block masks of the screened B when they were set for this nao.
@@ -404,6 +424,12 @@ void df_destroy(df_ctx* c) {
   (void)hipFree(c->status);
   if (c->blk_dev) (void)hipFree(c->blk_dev);
   (void)hipFree(c->aux);
+  for (hipStream_t w : c->workers) {
+    (void)hipStreamSynchronize(w);
+    (void)hipStreamDestroy(w);
+  }
+  for (hipEvent_t e : c->joins) (void)hipEventDestroy(e);
+  if (c->fork) (void)hipEventDestroy(c->fork);
   delete c;
 }
 
@@ -554,7 +580,7 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
            "x_fp64");
   } else {
     DF_HIP(launch_x_int8(st, s, B, naux, (int)nao, b_exp, dC, p.ncp, p.kp, fcol, (int)nocc, X, 1,
-                         xmax, p.pblk, D, rowdot, chunks_for(c, nao)),
+                         xmax, p.pblk, D, rowdot, chunks_for(c, nao), ksub_for(c, naux, nao, nocc)),
            "x_int8");
   }
   if (!per_block) {
@@ -874,6 +900,216 @@ int df_set_screening(df_ctx* c, const uint8_t* mask, const uint64_t* chunks, int
   c->scr_blk = blk;
   c->scr_nao = nao;
   return DF_OK;
+}
+
+// ------------------------------------------------------------- autotuning
+int df_autotune(df_ctx* c, const double* B, const int32_t* b_exp, int64_t naux, int64_t nao,
+                const double* C, int64_t nocc, double occ, const double* D, double* J, double* K,
+                double* energies, double* err_bound, int reps, int* best_groups, int* best_ksub,
+                double* best_ms) {
+  clear_stale_error();
+  int rc = check_shape(c, DF_DENSE, naux, nao, nocc);
+  if (rc) return rc;
+  if (reps < 1 || reps > 100) return fail(c, DF_EINVAL, "reps must be 1..100");
+  if (!c->blk_s.empty()) return fail(c, DF_EINVAL, "autotuning needs uniform precision");
+  const auto key = std::make_tuple(naux, nao, nocc, c->slices, c->pblk);
+  c->tuned.erase(key);
+  const int saved_req = c->k_groups_req;
+  c->k_groups_req = 0;
+  const Plan base = make_plan(c, naux, nao, nocc);
+  std::vector<int> groups = {base.groups};
+  for (int g = 1; g <= std::min(base.nb, 64); g *= 2)
+    if (g != base.groups) groups.push_back(g);
+  std::vector<int> ksubs = {1};
+  if (c->slices >= 1 && c->slices <= 5 && nao % 128 == 0) ksubs.push_back(2);
+  hipEvent_t e0, e1;
+  DF_HIP(hipEventCreate(&e0), "hipEventCreate");
+  DF_HIP(hipEventCreate(&e1), "hipEventCreate");
+  const int saved_cap = c->ev_cap;
+  c->ev_cap = 0;  // no stage marks while tuning
+  double best = 1e300;
+  std::pair<int, int> pick = {base.groups, 0};
+  rc = DF_OK;
+  for (int g : groups) {
+    for (int ks : ksubs) {
+      c->tuned[key] = {g, ks};
+      const Plan p = make_plan(c, naux, nao, nocc);
+      if (!c->ws || c->ws_bytes < p.total) continue;  // needs more workspace than given
+      rc = df_build_jk(c, B, DF_DENSE, naux, nao, b_exp, C, nocc, occ, D, J, K, energies, err_bound);
+      if (rc) break;
+      hipError_t e = hipEventRecord(e0, c->stream);
+      for (int r = 0; r < reps && e == hipSuccess && rc == DF_OK; ++r)
+        rc = df_build_jk(c, B, DF_DENSE, naux, nao, b_exp, C, nocc, occ, D, J, K, energies, err_bound);
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) rc = hip_fail(c, e, "autotune timing");
+      if (rc) break;
+      if (ms / reps < best) {
+        best = ms / reps;
+        pick = {g, ks};
+      }
+    }
+    if (rc) break;
+  }
+  c->ev_cap = saved_cap;
+  c->k_groups_req = saved_req;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    c->tuned.erase(key);
+    return rc;
+  }
+  if (best >= 1e300) return fail(c, DF_EWORKSPACE, "workspace too small for every candidate");
+  c->tuned[key] = pick;
+  if (best_groups) *best_groups = pick.first;
+  if (best_ksub) *best_ksub = pick.second;
+  if (best_ms) *best_ms = best;
+  return DF_OK;
+}
+
+// ------------------------------------------------------------- batched build
+namespace {
+
+double instance_cost(const df_problem& q) {
+  const double nn = (double)q.nao * q.nao;
+  const double pairs = q.slices ? q.slices * (q.slices + 1) / 2.0 : 8.0;
+  return nn * q.naux * (3.0 * q.nocc * pairs / 8.0 + 16.0);
+}
+
+// LPT: instances by cost, largest first, each onto the least-loaded stream.
+std::vector<std::vector<int>> assign(int n, const df_problem* q, int streams) {
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return instance_cost(q[a]) > instance_cost(q[b]); });
+  std::vector<std::vector<int>> out(streams);
+  std::vector<double> load(streams, 0.0);
+  for (int i : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    out[k].push_back(i);
+    load[k] += instance_cost(q[i]);
+  }
+  return out;
+}
+
+int batched_plan(df_ctx* c, int n, const df_problem* probs, int streams,
+                 std::vector<std::vector<int>>& groups, std::vector<size_t>& off, size_t& total) {
+  if (!c) return DF_EINVAL;
+  if (n < 1 || !probs) return fail(c, DF_EINVAL, "n >= 1 problems required");
+  if (streams < 1 || streams > 4) return fail(c, DF_EINVAL, "streams must be 1..4");
+  if (!c->blk_s.empty()) return fail(c, DF_EINVAL, "the batched build uses per-instance precision");
+  const int saved = c->slices;
+  for (int i = 0; i < n; ++i) {
+    const df_problem& q = probs[i];
+    int rc = check_shape(c, DF_DENSE, q.naux, q.nao, q.nocc);
+    if (rc) return rc;
+    if (q.slices < 0 || q.slices > kMaxSlices) return fail(c, DF_EINVAL, "slices must be 0..8");
+    if (!q.B || !q.C || !q.D || !q.J || !q.K || !q.energies || !q.err_bound)
+      return fail(c, DF_EINVAL, "null pointer in a problem");
+    rc = check_guard(c, q.slices, q.nao, q.nocc);
+    if (rc) return rc;
+  }
+  groups = assign(n, probs, streams);
+  off.assign(streams, 0);
+  total = 0;
+  for (int k = 0; k < streams; ++k) {
+    size_t need = 0;
+    for (int i : groups[k]) {
+      c->slices = probs[i].slices;
+      need = std::max(need, make_plan(c, probs[i].naux, probs[i].nao, probs[i].nocc).total);
+    }
+    off[k] = total;
+    total += (need + 255) / 256 * 256;
+  }
+  c->slices = saved;
+  return DF_OK;
+}
+
+}  // namespace
+
+int df_batched_workspace_size(df_ctx* c, int n, const df_problem* probs, int streams,
+                              size_t* bytes) {
+  std::vector<std::vector<int>> groups;
+  std::vector<size_t> off;
+  size_t total = 0;
+  const int rc = batched_plan(c, n, probs, streams, groups, off, total);
+  if (rc) return rc;
+  if (!bytes) return fail(c, DF_EINVAL, "null bytes");
+  *bytes = total;
+  return DF_OK;
+}
+
+int df_build_jk_batched(df_ctx* c, int n, const df_problem* probs, int streams) {
+  clear_stale_error();
+  std::vector<std::vector<int>> groups;
+  std::vector<size_t> off;
+  size_t total = 0;
+  int rc = batched_plan(c, n, probs, streams, groups, off, total);
+  if (rc) return rc;
+  if (!c->ws || c->ws_bytes < total) return fail(c, DF_EWORKSPACE, "workspace too small");
+  // worker streams (default priority) and their fork / join events
+  if (streams > 1 && !c->fork)
+    DF_HIP(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming), "hipEventCreate");
+  while (streams > 1 && (int)c->workers.size() < streams) {
+    hipStream_t w;
+    DF_HIP(hipStreamCreateWithFlags(&w, hipStreamNonBlocking), "hipStreamCreate");
+    c->workers.push_back(w);
+    hipEvent_t e;
+    DF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    c->joins.push_back(e);
+  }
+  hipStream_t home = c->stream;
+  char* ws = c->ws;
+  const size_t ws_bytes = c->ws_bytes;
+  const int saved_s = c->slices, saved_cap = c->ev_cap;
+  const uint8_t* saved_mask = c->scr_mask;
+  const unsigned long long* saved_chunks = c->scr_chunks;
+  const int saved_blk = c->scr_blk;
+  const int64_t saved_nao = c->scr_nao;
+  c->ev_cap = 0;
+  if (streams > 1) {
+    hipError_t e = hipEventRecord(c->fork, home);
+    for (int k = 0; k < streams && e == hipSuccess; ++k) e = hipStreamWaitEvent(c->workers[k], c->fork, 0);
+    if (e != hipSuccess) {
+      c->ev_cap = saved_cap;
+      return hip_fail(c, e, "fork");
+    }
+  }
+  for (int k = 0; k < streams && rc == DF_OK; ++k) {
+    c->stream = streams > 1 ? c->workers[k] : home;
+    c->ws = ws + off[k];
+    c->ws_bytes = (k + 1 < streams ? off[k + 1] : total) - off[k];
+    for (int i : groups[k]) {
+      const df_problem& q = probs[i];
+      c->slices = q.slices;
+      c->scr_mask = q.screen_mask;
+      c->scr_chunks = reinterpret_cast<const unsigned long long*>(q.screen_chunks);
+      c->scr_blk = q.screen_blk > 0 ? q.screen_blk : 8;
+      c->scr_nao = q.screen_mask ? q.nao : 0;
+      rc = df_build_jk(c, q.B, DF_DENSE, q.naux, q.nao, q.b_exp, q.C, q.nocc, q.occ, q.D, q.J, q.K,
+                       q.energies, q.err_bound);
+      if (rc) break;
+    }
+  }
+  if (streams > 1) {
+    for (int k = 0; k < streams; ++k) {
+      const hipError_t e1 = hipEventRecord(c->joins[k], c->workers[k]);
+      const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(home, c->joins[k], 0) : e1;
+      if (e2 != hipSuccess && rc == DF_OK) rc = hip_fail(c, e2, "join");
+    }
+  }
+  c->stream = home;
+  c->ws = ws;
+  c->ws_bytes = ws_bytes;
+  c->slices = saved_s;
+  c->ev_cap = saved_cap;
+  c->scr_mask = saved_mask;
+  c->scr_chunks = saved_chunks;
+  c->scr_blk = saved_blk;
+  c->scr_nao = saved_nao;
+  return rc;
 }
 
 int df_timing_begin(df_ctx* c, int max_calls) {

@@ -135,7 +135,9 @@ hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, i
                          const int32_t* b_exp, const int8_t* dC, int ncp, int kp,
                          const int32_t* f_col, int nocc, double* X, int xlayout,
                          unsigned long long* xmax, int pblk, const double* D, double* rowdot,
-                         const unsigned long long* cmask = nullptr);
+                         const unsigned long long* cmask = nullptr, int ksub = 0);
+// (ksub: k depth per LDS stage, 1 = 64, 2 = 128 where s <= 5 and nao % 128 == 0,
+// 0 = the default choice.)
 // X in the blocked layout.
 hipError_t launch_slice_x(hipStream_t st, int s, const double* Xb, int64_t naux, int nao,
                           int nocc, int pblk, int nao_pad, int kbp,
