@@ -155,6 +155,184 @@ def adaptive_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def controller_workload(args):
+    """Learned controller vs the plain rule on a 30-iteration sequence."""
+    import numpy as np
+    import torch
+    import dfinputs
+    from paper_2601_08077_amd import Context, adaptive, controller
+
+    ctx = Context()
+    ctx.df_set_pblk(64)
+    t0 = time.perf_counter()
+    xs, ts, ms_ = [], [], []
+    for seed in (11, 12, 13):
+        p = dfinputs.make_problem_device(nao=512, naux=2048, nocc=64, L=16.0, seed=seed,
+                                         block_scale=4)
+        orbs = [torch.from_numpy(c).cuda() for c in
+                dfinputs.perturbed_orbitals(p["C_host"], 10, seed=seed)]
+        be = torch.empty(2048 * 512, dtype=torch.int32, device="cuda")
+        ctx.df_b_exponents(p["B"], be)
+        x, t, m = controller.collect_samples(ctx, p["B"], be, orbs)
+        xs.append(x), ts.append(t), ms_.append(m)
+        del p, orbs, be
+    x, t, m = np.concatenate(xs), np.concatenate(ts), np.concatenate(ms_)
+    t_samples = time.perf_counter() - t0
+    log(f"controller: {x.shape[0]} samples in {t_samples:.1f} s")
+    t0 = time.perf_counter()
+    params, losses = controller.train(ctx, x, t, m, steps=3000, batch=256, lr=3e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    rms = controller.evaluate(ctx, params, x, t, m)
+    log(f"controller: trained 3000 steps in {t_train:.2f} s, rms {rms:.3f} decades")
+
+    nao, naux, nocc, n_iter = args.ctl_nao, 4 * args.ctl_nao, args.ctl_nao // 8, 30
+    log(f"controller: evaluation sequence nao {nao} naux {naux} nocc {nocc}, {n_iter} iterations")
+    p = dfinputs.make_problem_device(nao=nao, naux=naux, nocc=nocc, L=24.0, seed=0, block_scale=4)
+    B = p["B"]
+    orbs = [torch.from_numpy(c).cuda() for c in
+            dfinputs.perturbed_orbitals(p["C_host"], n_iter, seed=0)]
+    be = torch.empty(naux * nao, dtype=torch.int32, device="cuda")
+    ctx.df_b_exponents(B, be)
+    ctx.df_set_block_precision(None)
+    ctx.ensure_workspace(naux, nao, nocc)
+    D = torch.empty((nao, nao), dtype=torch.float64, device="cuda")
+    J, K = torch.empty_like(D), torch.empty_like(D)
+    en = torch.empty(2, dtype=torch.float64, device="cuda")
+    eb = torch.empty(1, dtype=torch.float64, device="cuda")
+    ctx.df_density(orbs[0], 2.0, D)
+    times, below = adaptive.calibrate(ctx, B, be, orbs[0], 2.0, D, J, K, en, eb)
+    log(f"controller: calibration ms {times}, FP64 from level {below} down")
+    plain = adaptive.run_sequence(ctx, B, be, orbs, fp64_below_level=below, judge=True)
+    ctl = controller.run_controlled(ctx, B, be, orbs, params, fp64_below_level=below, judge=True)
+    nb = (naux + 63) // 64
+    w_plain = sum(nb * r["slices"] * (r["slices"] + 1) // 2 for r in plain)
+    w_ctl = sum(r["work"] for r in ctl)
+    ms_plain = sum(r["ms"] for r in plain)
+    ms_ctl = sum(r["ms"] for r in ctl)
+    for a, c in zip(plain, ctl):
+        log(f"it {a['iteration']:2d} plain s={a['slices']} {a['ms']:.1f} ms err "
+            f"{a['k_maxabs_rel_fro']:.2e} | ctl ref {c['s_ref']} work {c['work']}/{c['work_ref']} "
+            f"{c['ms']:.1f} ms err {c['k_maxabs_rel_fro']:.2e} fb {c['fallback']}")
+    F = flops_alg(nao, naux, nocc)
+    out = {"metric": METRIC, "value": F * len(ctl) / ms_ctl / 1e9, "unit": "TFLOP/s",
+           "n_gpus": 1, "steps": len(ctl), "warmup": 0, "ms_per_step": ms_ctl / len(ctl),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int8 x int8 -> int32, f64 recombination (per-block s), f32 controller",
+           "data": "synthetic",
+           "config": {"workload": f"learned controller vs plain rule, nao {nao} naux {naux} "
+                                  f"nocc {nocc}, {n_iter} iterations, eps 1e-2 -> 1e-8, "
+                                  "per-64-aux-block scale 10^U(-4,0)",
+                      "training": "3 sequences nao 512 naux 2048 nocc 64 x 10 iterations",
+                      "fp64_below_level": below},
+           "samples": int(x.shape[0]), "sample_seconds": t_samples, "train_seconds": t_train,
+           "train_rms_decades": rms, "loss_first": float(losses[0]),
+           "loss_last": float(losses[-50:].mean()),
+           "plain_total_ms": ms_plain, "controller_total_ms": ms_ctl,
+           "speedup_vs_plain": ms_plain / ms_ctl,
+           "digit_products_plain": w_plain, "digit_products_controller": w_ctl,
+           "fallbacks": sum(1 for r in ctl if r["fallback"]),
+           "max_k_err_plain": max(r["k_maxabs_rel_fro"] for r in plain),
+           "max_k_err_controller": max(r["k_maxabs_rel_fro"] for r in ctl),
+           "final_energy_err_plain": plain[-1]["energy_err"],
+           "final_energy_err_controller": ctl[-1]["energy_err"],
+           "calibration_ms": {str(k): v for k, v in times.items()},
+           "iterations_plain": plain, "iterations_controller": ctl}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def batched_workload(args):
+    """48 uneven screened instances: one-by-one builds vs the batched build."""
+    import numpy as np
+    import torch
+    import dfinputs
+    from paper_2601_08077_amd import Context
+
+    rng = np.random.default_rng(0)
+    naos = [int(v) for v in 8 * rng.integers(16, args.batch_max_nao // 8 + 1, 48)]
+    ctx = Context()
+    ctx.df_set_pblk(64)
+    insts = []
+    kept = []
+    log(f"batched: generating 48 instances, nao {min(naos)}..{max(naos)}")
+    for i, nao in enumerate(naos):
+        naux, nocc = 4 * nao, nao // 8
+        p = dfinputs.make_problem_device(nao=nao, naux=naux, nocc=nocc, L=12.0, seed=1000 + i)
+        nblk = nao // 8
+        mask = torch.empty((nblk, nblk), dtype=torch.uint8, device="cuda")
+        chunks = torch.empty(nao, dtype=torch.int64, device="cuda")
+        ctx.df_screen(p["B"], 8, 1e-10, mask, chunks)
+        kept.append(float(mask.float().mean()))
+        outs = dict(J=torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+                    K=torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+                    en=torch.empty(2, dtype=torch.float64, device="cuda"),
+                    eb=torch.empty(1, dtype=torch.float64, device="cuda"))
+        insts.append(dict(B=p["B"], C=p["C"], D=p["D"], mask=mask, chunks=chunks, **outs))
+    torch.cuda.synchronize()
+    s = args.slices
+    F = sum(flops_alg(i["B"].shape[1], i["B"].shape[0], i["C"].shape[1]) for i in insts)
+
+    def one_by_one():
+        for i in insts:
+            nao = i["B"].shape[1]
+            ctx.df_set_screening(i["mask"], i["chunks"], 8, nao)
+            ctx.df_build_jk(i["B"], None, i["C"], 2.0, i["D"], i["J"], i["K"], i["en"], i["eb"])
+        ctx.df_set_screening(None, None, 8, 0)
+
+    ctx.df_set_precision(s)
+    need = max(ctx.df_workspace_size(i["B"].shape[0], i["B"].shape[1], i["C"].shape[1])
+               for i in insts)
+    ctx.df_set_workspace(torch.empty(need, dtype=torch.uint8, device="cuda"))
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_seq = timed(one_by_one, args.steps)
+    log(f"batched: one by one {ms_seq:.2f} ms")
+    # autotune every distinct shape (kept in the context for the batched run)
+    t0 = time.perf_counter()
+    for i in insts:
+        nao = i["B"].shape[1]
+        ctx.df_set_screening(i["mask"], i["chunks"], 8, nao)
+        ctx.df_autotune(i["B"], None, i["C"], 2.0, i["D"], i["J"], i["K"], i["en"], i["eb"], reps=2)
+    ctx.df_set_screening(None, None, 8, 0)
+    t_tune = time.perf_counter() - t0
+    probs = [ctx.make_problem(i["B"], i["C"], i["D"], i["J"], i["K"], i["en"], i["eb"], s,
+                              screen_mask=i["mask"], screen_chunks=i["chunks"]) for i in insts]
+    res = {}
+    for streams in (1, 4):
+        need = ctx.df_batched_workspace_size(probs, streams)
+        ctx.df_set_workspace(None)
+        ctx.df_set_workspace(torch.empty(need, dtype=torch.uint8, device="cuda"))
+        res[streams] = timed(lambda: ctx.df_build_jk_batched(probs, streams), args.steps)
+        log(f"batched: {streams} stream(s), tuned shapes: {res[streams]:.2f} ms")
+    ms = res[4]
+    out = {"metric": METRIC, "value": F / ms / 1e9, "unit": "TFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "int8 x int8 -> int32, f64 recombination" if s else "f64",
+           "data": "synthetic",
+           "config": {"workload": f"48 uneven instances, nao 8Z in [128, {args.batch_max_nao}], "
+                                  "naux 4 nao, nocc nao/8, L 12, shell blocks of 8 screened at "
+                                  "1e-10", "slices": s, "naos": naos},
+           "one_by_one_ms": ms_seq, "batched_1stream_tuned_ms": res[1],
+           "batched_4streams_tuned_ms": res[4], "speedup_vs_one_by_one": ms_seq / ms,
+           "autotune_seconds": t_tune, "kept_block_fraction_mean": float(np.mean(kept)),
+           "flops_alg_total": F}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,9 +345,16 @@ def main():
     ap.add_argument("--no-sliced", action="store_true",
                     help="skip the sliced-mode levels (B as digit planes, digit rho and J)")
     ap.add_argument("--cpu-aux", type=int, default=64)
-    ap.add_argument("--workload", choices=("jk", "adaptive"), default="jk",
+    ap.add_argument("--workload", choices=("jk", "adaptive", "controller", "batched"),
+                    default="jk",
                     help="jk: one J/K build per step (default); adaptive: the 20-iteration "
-                         "adaptive-precision sequence with metric Cholesky and whitening")
+                         "adaptive-precision sequence with metric Cholesky and whitening; "
+                         "controller: learned per-block controller vs the plain rule; "
+                         "batched: 48 uneven screened instances, batched vs one by one")
+    ap.add_argument("--ctl-nao", type=int, default=1536,
+                    help="nao of the controller evaluation sequence (naux = 4 nao, nocc = nao/8)")
+    ap.add_argument("--batch-max-nao", type=int, default=512,
+                    help="largest nao of the batched instances")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (scales HBM byte counters)")
     args = ap.parse_args()
@@ -195,6 +380,10 @@ def main():
 
     if args.workload == "adaptive":
         return adaptive_workload(args)
+    if args.workload == "controller":
+        return controller_workload(args)
+    if args.workload == "batched":
+        return batched_workload(args)
 
     cfg = dfinputs.CONFIG1
     nao, naux, nocc = cfg["nao"], cfg["naux"], cfg["nocc"]

@@ -66,6 +66,21 @@ __host__ __device__ inline double kappa_of(int s, int64_t k) {
   return 2.0 * eps + eps * eps + dropped + rounding;
 }
 
+// Byte offset of 16-byte unit `unit` (0..3) of a 64-byte LDS row: the units are
+// XOR-swizzled with bits 1..2 of the row, so that the 16 rows of an MFMA
+// fragment read (16 lanes, one unit each) spread over all LDS banks.
+__device__ __forceinline__ int swz(int row, int unit) { return (unit ^ ((row >> 1) & 3)) << 4; }
+
+// Workgroups are handed to the 8 XCDs of the chip round-robin by linear id,
+// and each XCD has its own L2.  xcd_order(id, n) renumbers the n workgroups of a
+// launch so that XCD x receives the consecutive logical range
+// [x n / 8, (x + 1) n / 8) (a bijection on [0, n)): logically adjacent work
+// items that share operands then meet in one L2.
+__device__ __forceinline__ int64_t xcd_order(int64_t id, int64_t n) {
+  const int64_t x = id & 7, i = id >> 3, q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // Set bits of a chunk mask: the first one, and the first one above c (-1: none).
 __device__ __forceinline__ int first_bit(unsigned long long m) {
   return m ? __ffsll((unsigned long long)m) - 1 : -1;

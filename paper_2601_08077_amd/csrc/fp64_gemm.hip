@@ -156,9 +156,13 @@ __global__ __launch_bounds__(256) void k_k_fp64(const double* __restrict__ Xb, i
                                                 double* __restrict__ Kp) {
   __shared__ double As[2][64][17];
   __shared__ double Bs[2][64][17];
+  // group-major logical order, dealt to the XCDs in consecutive ranges (the
+  // tiles of one group share X_b panels in one L2)
+  const int64_t ntile = gridDim.x;
+  const int64_t lid = xcd_order(blockIdx.x + (int64_t)blockIdx.y * ntile, ntile * gridDim.y);
+  const int grp = (int)(lid / ntile);
   int t1, t2;
-  lower_tile(blockIdx.x, t1, t2);
-  const int grp = blockIdx.y;
+  lower_tile((int)(lid - grp * ntile), t1, t2);
   const int b_lo = (int)((int64_t)grp * nb / groups), b_hi = (int)((int64_t)(grp + 1) * nb / groups);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
     const double* __restrict__ D, double* __restrict__ rowdot,
     const unsigned long long* __restrict__ cmask) {
   constexpr int NT = 16 * NF, NFW = NF / 2;
-  constexpr int KC = 64 * KSUB, ROW = KC + 16;  // LDS rows: KC k bytes + 16 B pad
+  constexpr int KC = 64 * KSUB, ROW = KC;  // LDS rows: KC k bytes, units swizzled per 64 B
   constexpr int CUNITS = S * NT * 4 * KSUB;     // 16-byte units of C digits per chunk
   constexpr int CPER = (CUNITS + 511) / 512;
   constexpr int NV = 8 * KSUB;                  // B values sliced per lane per chunk
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
   const bool want_rd = D != nullptr;
   const double* drow = (want_rd ? D : B) + (aok ? (arow % nao) : 0) * (int64_t)K + 2 * q + 32 * half;
   const int nch = (K + KC - 1) / KC;
-  int8_t* adst = &As[0][wrow * 16 + r16][q * 16 + half * 8];
+  int8_t* adst = &As[0][wrow * 16 + r16][swz(wrow * 16 + r16, q) + half * 8];
   // Screened B: only the KC-wide nu chunks that meet a kept block in some row
   // of this tile are visited (the rest of the tile is zero).
   const unsigned long long live = cmask ? tile_chunks<KSUB>(cmask, m0, M, nao, w, l) : 0ull;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
     const int a = uu / per_plane, rem = uu - a * per_plane;
     const int col = rem / (4 * KSUB), part = rem - col * (4 * KSUB);
     csrc[i] = dC + ((int64_t)a * ncp + n0 + col) * kp + part * 16;
-    cdst[i] = (a * NT + col) * ROW + part * 16;
+    cdst[i] = (a * NT + col) * ROW + (part >> 2) * 64 + swz(col, part & 3);
   }
 
   i32x4 acc[S][NFW];
@@ -174,14 +174,15 @@ __global__ __launch_bounds__(512) void k_x_int8(
       i32x4 af[S];
 #pragma unroll
       for (int a = 0; a < S; ++a)
-        af[a] = *reinterpret_cast<const i32x4*>(&As[a][wrow * 16 + r16][sub * 64 + q * 16]);
+        af[a] = *reinterpret_cast<const i32x4*>(
+            &As[a][wrow * 16 + r16][sub * 64 + swz(wrow * 16 + r16, q)]);
 #pragma unroll
       for (int f = 0; f < NFW; ++f) {
         i32x4 bf[S];
 #pragma unroll
         for (int b = 0; b < S; ++b)
           bf[b] = *reinterpret_cast<const i32x4*>(
-              &Cs[b][(half * NFW + f) * 16 + r16][sub * 64 + q * 16]);
+              &Cs[b][(half * NFW + f) * 16 + r16][sub * 64 + swz((half * NFW + f) * 16 + r16, q)]);
 #pragma unroll
         for (int a = 0; a < S; ++a)
 #pragma unroll
@@ -312,12 +313,16 @@ __global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
                                                 const int32_t* __restrict__ F, int nb, int nao,
                                                 int nao_pad, int kbp, int groups,
                                                 double* __restrict__ Kp) {
-  constexpr int ROW = 80;  // 64 B + 16 B pad: conflict-free 16-byte fragment reads
+  constexpr int ROW = 64;  // 64 B rows, 16-byte units swizzled (swz)
   __shared__ __attribute__((aligned(16))) int8_t Ls[2][S][64][ROW];
+  // group-major logical order, dealt to the XCDs in consecutive ranges: the
+  // tiles of one group (which stream the same X_b panels) share an L2
+  const int64_t ntile = gridDim.x;
+  const int64_t lid = xcd_order(blockIdx.x + (int64_t)blockIdx.y * ntile, ntile * gridDim.y);
+  const int grp = (int)(lid / ntile);
   int t1, t2;
-  lower_tile(blockIdx.x, t1, t2);
+  lower_tile((int)(lid - grp * ntile), t1, t2);
   const bool diag = t1 == t2;
-  const int grp = blockIdx.y;
   const int b_lo = (int)((int64_t)grp * nb / groups);
   const int b_hi = (int)((int64_t)(grp + 1) * nb / groups);
   const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
@@ -328,7 +333,7 @@ __global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
   const int lrow = t >> 2, lpart = t & 3;
   const int8_t* srcA = Xd + (int64_t)(t1 * 64 + lrow) * kbp + lpart * 16;
   const int8_t* srcB = Xd + (int64_t)(t2 * 64 + lrow) * kbp + lpart * 16;
-  const int ldst = lrow * ROW + lpart * 16;
+  const int ldst = lrow * ROW + swz(lrow, lpart);
   i32x4 preA[S], preB[S];
 #define DFJK_K_LOAD_STEP(BB, K0)                                                               \
   {                                                                                            \
@@ -374,13 +379,14 @@ __global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
       for (int bb = 0; bb < S; ++bb)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          bf[bb][j] = *reinterpret_cast<const i32x4*>(&Ls[1][bb][wc + j * 16 + r16][q * 16]);
+          bf[bb][j] = *reinterpret_cast<const i32x4*>(
+              &Ls[1][bb][wc + j * 16 + r16][swz(wc + j * 16 + r16, q)]);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         i32x4 af[S];
 #pragma unroll
         for (int a = 0; a < S; ++a)
-          af[a] = *reinterpret_cast<const i32x4*>(&Ls[0][a][wr + i * 16 + r16][q * 16]);
+          af[a] = *reinterpret_cast<const i32x4*>(&Ls[0][a][wr + i * 16 + r16][swz(wr + i * 16 + r16, q)]);
 #pragma unroll
         for (int a = 0; a < S; ++a)
 #pragma unroll

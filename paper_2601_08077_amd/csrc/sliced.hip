@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256 * NH) void k_x_dig(
     const int32_t* __restrict__ f_col, int nocc, double* __restrict__ X,
     unsigned long long* __restrict__ xmax, int nao, int pblk,
     const int8_t* __restrict__ Dd, const int32_t* __restrict__ d_exp, double* __restrict__ rowdot) {
-  constexpr int NF = NFW * NH, NT = 16 * NF, ROW = 80, NTHR = 256 * NH;
+  constexpr int NF = NFW * NH, NT = 16 * NF, ROW = 64, NTHR = 256 * NH;
   constexpr int CUNITS = S * NT * 4;
   constexpr int CPER = (CUNITS + NTHR - 1) / NTHR;
   __shared__ __attribute__((aligned(16))) int8_t Cs[S][NT][ROW];
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256 * NH) void k_x_dig(
     const int uu = u < CUNITS ? u : 0;
     const int a = uu / (NT * 4), rem = uu - a * (NT * 4), col = rem >> 2, part = rem & 3;
     csrc[i] = dC + ((int64_t)a * ncp + n0 + col) * ldk + part * 16;
-    cdst[i] = (a * NT + col) * ROW + part * 16;
+    cdst[i] = (a * NT + col) * ROW + swz(col, part);
   }
 
   i32x4 acc[S][NFW];
@@ -158,7 +158,8 @@ __global__ __launch_bounds__(256 * NH) void k_x_dig(
       i32x4 bf[S];
 #pragma unroll
       for (int b = 0; b < S; ++b)
-        bf[b] = *reinterpret_cast<const i32x4*>(&Cs[b][(half * NFW + f) * 16 + r16][q * 16]);
+        bf[b] = *reinterpret_cast<const i32x4*>(
+            &Cs[b][(half * NFW + f) * 16 + r16][swz((half * NFW + f) * 16 + r16, q)]);
 #pragma unroll
       for (int a = 0; a < S; ++a)
 #pragma unroll
