@@ -51,8 +51,11 @@ __global__ __launch_bounds__(512) void k_x_int8(
   constexpr int CUNITS = S * NT * 4 * KSUB;     // 16-byte units of C digits per chunk
   constexpr int CPER = (CUNITS + 511) / 512;
   constexpr int NV = 8 * KSUB;                  // B values sliced per lane per chunk
-  __shared__ __attribute__((aligned(16))) int8_t As[S][64][ROW];
-  __shared__ __attribute__((aligned(16))) int8_t Cs[S][NT][ROW];
+  // Two LDS stages when they fit (KSUB == 1): the digits of chunk c + 1 are
+  // written while chunk c is multiplied, one barrier per chunk.
+  constexpr int NBUF = (KSUB == 1 && 2 * S * (64 + NT) * ROW + 1024 <= 160 * 1024) ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) int8_t As[NBUF][S][64][ROW];
+  __shared__ __attribute__((aligned(16))) int8_t Cs[NBUF][S][NT][ROW];
   __shared__ double rdx[4][16];
 
   const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
@@ -77,7 +80,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
   const bool want_rd = D != nullptr;
   const double* drow = (want_rd ? D : B) + (aok ? (arow % nao) : 0) * (int64_t)K + 2 * q + 32 * half;
   const int nch = (K + KC - 1) / KC;
-  int8_t* adst = &As[0][wrow * 16 + r16][swz(wrow * 16 + r16, q) + half * 8];
+  int8_t* adst = &As[0][0][wrow * 16 + r16][swz(wrow * 16 + r16, q) + half * 8];
   // Screened B: only the KC-wide nu chunks that meet a kept block in some row
   // of this tile are visited (the rest of the tile is zero).
   const unsigned long long live = cmask ? tile_chunks<KSUB>(cmask, m0, M, nao, w, l) : 0ull;
@@ -135,64 +138,83 @@ __global__ __launch_bounds__(512) void k_x_int8(
     }                                                                                      \
   }
 
-  int c = cmask ? first_bit(live) : (nch > 0 ? 0 : -1);
-  if (c >= 0) DFJK_X_LOAD(c)
-  while (c >= 0) {
-    const int cn = cmask ? next_bit(live, c) : (c + 1 < nch ? c + 1 : -1);
-    // slice this lane's values into S digit planes (8 bytes per sub-chunk)
-    uint32_t lo[KSUB][S], hi[KSUB][S];
-    {
-      if (want_rd) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) rd = fma(v[j], dv[j], rd);
-      }
-#pragma unroll
-      for (int sub = 0; sub < KSUB; ++sub) {
-        uint64_t wd[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) wd[j] = digit_word(v[8 * sub + j], e_a);
-#pragma unroll
-        for (int a = 0; a < S; ++a) {
-          lo[sub][a] = pack4(wd[0], wd[1], wd[2], wd[3], a + 1);
-          hi[sub][a] = pack4(wd[4], wd[5], wd[6], wd[7], a + 1);
-        }
-      }
-    }
-    __syncthreads();  // previous chunk's LDS reads are done
-#pragma unroll
-    for (int sub = 0; sub < KSUB; ++sub)
-#pragma unroll
-      for (int a = 0; a < S; ++a)
-        *reinterpret_cast<uint2*>(adst + a * 64 * ROW + sub * 64) = make_uint2(lo[sub][a], hi[sub][a]);
-#pragma unroll
-    for (int i = 0; i < CPER; ++i)
-      if (t + 512 * i < CUNITS) *reinterpret_cast<i32x4*>(&Cs[0][0][0] + cdst[i]) = cpre[i];
-    __syncthreads();  // A and C digits of chunk c are in LDS
-    if (cn >= 0) DFJK_X_LOAD(cn)
-#pragma unroll
-    for (int sub = 0; sub < KSUB; ++sub) {
-      i32x4 af[S];
-#pragma unroll
-      for (int a = 0; a < S; ++a)
-        af[a] = *reinterpret_cast<const i32x4*>(
-            &As[a][wrow * 16 + r16][sub * 64 + swz(wrow * 16 + r16, q)]);
-#pragma unroll
-      for (int f = 0; f < NFW; ++f) {
-        i32x4 bf[S];
-#pragma unroll
-        for (int b = 0; b < S; ++b)
-          bf[b] = *reinterpret_cast<const i32x4*>(
-              &Cs[b][(half * NFW + f) * 16 + r16][sub * 64 + swz((half * NFW + f) * 16 + r16, q)]);
-#pragma unroll
-        for (int a = 0; a < S; ++a)
-#pragma unroll
-          for (int b = 0; b < S - a; ++b)
-            acc[a + b][f] =
-                __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a + b][f], 0, 0, 0);
-      }
-    }
-    c = cn;
+  // Digits of the chunk whose B values and C digits sit in registers, into
+  // LDS stage BUF (and its B.D row-dot terms into rd).
+#define DFJK_X_STAGE(BUF)                                                                       \
+  {                                                                                             \
+    if (want_rd) {                                                                              \
+      _Pragma("unroll") for (int j = 0; j < NV; ++j) rd = fma(v[j], dv[j], rd);                 \
+    }                                                                                           \
+    _Pragma("unroll") for (int sub = 0; sub < KSUB; ++sub) {                                    \
+      uint64_t wd[8];                                                                           \
+      _Pragma("unroll") for (int j = 0; j < 8; ++j) wd[j] = digit_word(v[8 * sub + j], e_a);    \
+      _Pragma("unroll") for (int a = 0; a < S; ++a)                                             \
+        *reinterpret_cast<uint2*>(adst + ((BUF) * S + a) * 64 * ROW + sub * 64) =               \
+            make_uint2(pack4(wd[0], wd[1], wd[2], wd[3], a + 1),                                \
+                       pack4(wd[4], wd[5], wd[6], wd[7], a + 1));                               \
+    }                                                                                           \
+    _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                          \
+      if (t + 512 * i < CUNITS)                                                                 \
+        *reinterpret_cast<i32x4*>(&Cs[BUF][0][0][0] + cdst[i]) = cpre[i];                       \
+    }                                                                                           \
   }
+  // MFMAs of the chunk held in LDS stage BUF.
+#define DFJK_X_MMA(BUF)                                                                         \
+  _Pragma("unroll") for (int sub = 0; sub < KSUB; ++sub) {                                      \
+    i32x4 af[S];                                                                                \
+    _Pragma("unroll") for (int a = 0; a < S; ++a) af[a] = *reinterpret_cast<const i32x4*>(      \
+        &As[BUF][a][wrow * 16 + r16][sub * 64 + swz(wrow * 16 + r16, q)]);                      \
+    _Pragma("unroll") for (int f = 0; f < NFW; ++f) {                                           \
+      const int col = (half * NFW + f) * 16 + r16;                                              \
+      i32x4 bf[S];                                                                              \
+      _Pragma("unroll") for (int b = 0; b < S; ++b) bf[b] =                                     \
+          *reinterpret_cast<const i32x4*>(&Cs[BUF][b][col][sub * 64 + swz(col, q)]);            \
+      _Pragma("unroll") for (int a = 0; a < S; ++a)                                             \
+        _Pragma("unroll") for (int b = 0; b < S - a; ++b) acc[a + b][f] =                       \
+            __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a + b][f], 0, 0, 0);        \
+    }                                                                                           \
+  }
+
+  int c = cmask ? first_bit(live) : (nch > 0 ? 0 : -1);
+  auto next_of = [&](int cc) {
+    return cc < 0 ? -1 : (cmask ? next_bit(live, cc) : (cc + 1 < nch ? cc + 1 : -1));
+  };
+  if constexpr (NBUF == 2) {
+    // stage c into LDS 0, prefetch the next chunk into registers; then per
+    // chunk: stage the next chunk into the other LDS buffer, prefetch the
+    // one after, multiply the current one, one barrier.
+    int cn = next_of(c);
+    if (c >= 0) {
+      DFJK_X_LOAD(c)
+      DFJK_X_STAGE(0)
+    }
+    if (cn >= 0) DFJK_X_LOAD(cn)
+    __syncthreads();
+    int buf = 0;
+    while (c >= 0) {
+      const int cnn = next_of(cn);
+      if (cn >= 0) DFJK_X_STAGE(buf ^ 1)
+      if (cnn >= 0) DFJK_X_LOAD(cnn)
+      DFJK_X_MMA(buf)
+      __syncthreads();  // stage buf may be overwritten, stage buf ^ 1 is complete
+      buf ^= 1;
+      c = cn;
+      cn = cnn;
+    }
+  } else {
+    if (c >= 0) DFJK_X_LOAD(c)
+    while (c >= 0) {
+      const int cn = next_of(c);
+      __syncthreads();  // the previous chunk's LDS reads are done
+      DFJK_X_STAGE(0)
+      __syncthreads();  // A and C digits of chunk c are in LDS
+      if (cn >= 0) DFJK_X_LOAD(cn)
+      DFJK_X_MMA(0)
+      c = cn;
+    }
+  }
+#undef DFJK_X_MMA
+#undef DFJK_X_STAGE
 #undef DFJK_X_LOAD
 
   if (rowdot) {
