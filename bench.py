@@ -38,16 +38,49 @@ def flops_paper(nao, naux, nocc, nscr=None):
 
 
 def stage_units(stage, s, nao, naux, nocc):
-    """Algorithmic (ops, bytes) of one launch of a stage; ops are INT8 ops for s >= 1."""
+    """Algorithmic (ops, bytes) of one launch of a stage; ops are INT8 ops for s >= 1.
+
+    x: the B.C products (and the B.D row dots of rho, fused) read B once and
+    write X; k: the symmetric products read the digits of X (FP64 X for s = 0);
+    rho: the sum of the row dots; j: the lower triangle of B once."""
     npairs = s * (s + 1) // 2 if s else 1
     nn = nao * nao
     if stage == "x":
-        return npairs * 2 * naux * nao * nao * nocc, 8 * naux * nn + 8 * naux * nao * nocc
+        return npairs * 2 * naux * nn * nocc, 8 * naux * nn + 8 * naux * nao * nocc
     if stage == "k":
         return npairs * nao * (nao + 1) * naux * nocc, (s if s else 8) * naux * nao * nocc
-    if stage in ("rho", "j"):
-        return 2 * naux * nn, 8 * naux * nn
+    if stage == "rho":
+        return naux * nao, 8 * naux * nao
+    if stage == "j":
+        ntri = nao * (nao + 1) // 2
+        return 2 * naux * ntri, 8 * naux * ntri
     return 0, 0
+
+
+def measured_traffic(stage, s):
+    """HBM bytes per launch of a stage's kernel from a committed counter record
+    (profiles/traffic_*.json: FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy),
+    or None when there is none or a source it covers has changed since."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    for path in sorted(glob.glob(os.path.join(here, "profiles", "traffic_*.json"))):
+        try:
+            rec = json.load(open(path))
+        except (OSError, ValueError):
+            continue
+        if rec.get("stage") != stage or rec.get("slices") != s:
+            continue
+        fresh = True
+        for src, digest in rec.get("sources_sha256", {}).items():
+            try:
+                cur = hashlib.sha256(open(os.path.join(here, src), "rb").read()).hexdigest()
+            except OSError:
+                cur = None
+            fresh = fresh and cur == digest
+        if fresh:
+            return rec.get("traffic_bytes_per_launch")
+    return None
 
 
 def roofline_of(stage, ms, s, nao, naux, nocc):
@@ -59,11 +92,12 @@ def roofline_of(stage, ms, s, nao, naux, nocc):
     if t_comp >= t_mem:
         ach = ops / sec / 1e12
         return {"bound": "mfma", "achieved": ach, "peak": comp_peak, "unit": "TFLOP/s",
-                "frac": ach / comp_peak, "traffic": None, "kernel": stage,
+                "frac": ach / comp_peak, "traffic": measured_traffic(stage, s), "kernel": stage,
                 "ops_per_launch": ops, "ops_kind": "int8 ops" if s else "fp64 flops"}
     ach = byts / sec / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
-            "frac": ach / PEAK["hbm"], "traffic": None, "kernel": stage, "bytes_per_launch": byts}
+            "frac": ach / PEAK["hbm"], "traffic": measured_traffic(stage, s), "kernel": stage,
+            "bytes_per_launch": byts}
 
 
 def cpu_baseline(s, naux_sample, nao, nocc, L):
