@@ -200,12 +200,13 @@ def controller_workload(args):
     ctx.df_set_pblk(64)
     t0 = time.perf_counter()
     xs, ts, ms_ = [], [], []
-    for seed in (11, 12, 13):
-        p = dfinputs.make_problem_device(nao=512, naux=2048, nocc=64, L=16.0, seed=seed,
-                                         block_scale=4)
+    for seed, tnao, tL in ((11, 256, 16.0), (12, 512, 24.0), (13, 768, 24.0), (14, 1024, 24.0),
+                           (15, 1280, 24.0)):
+        p = dfinputs.make_problem_device(nao=tnao, naux=4 * tnao, nocc=tnao // 8, L=tL,
+                                         seed=seed, block_scale=4)
         orbs = [torch.from_numpy(c).cuda() for c in
                 dfinputs.perturbed_orbitals(p["C_host"], 10, seed=seed)]
-        be = torch.empty(2048 * 512, dtype=torch.int32, device="cuda")
+        be = torch.empty(4 * tnao * tnao, dtype=torch.int32, device="cuda")
         ctx.df_b_exponents(p["B"], be)
         x, t, m = controller.collect_samples(ctx, p["B"], be, orbs)
         xs.append(x), ts.append(t), ms_.append(m)
@@ -238,7 +239,10 @@ def controller_workload(args):
     times, below = adaptive.calibrate(ctx, B, be, orbs[0], 2.0, D, J, K, en, eb)
     log(f"controller: calibration ms {times}, FP64 from level {below} down")
     plain = adaptive.run_sequence(ctx, B, be, orbs, fp64_below_level=below, judge=True)
-    ctl = controller.run_controlled(ctx, B, be, orbs, params, fp64_below_level=below, judge=True)
+    # the controller takes the plain run's reference count in every iteration, so the
+    # two are compared at the same reference accuracy
+    ctl = controller.run_controlled(ctx, B, be, orbs, params, fp64_below_level=below, judge=True,
+                                    s_refs=[r["slices"] for r in plain])
     nb = (naux + 63) // 64
     w_plain = sum(nb * r["slices"] * (r["slices"] + 1) // 2 for r in plain)
     w_ctl = sum(r["work"] for r in ctl)
@@ -257,7 +261,8 @@ def controller_workload(args):
            "config": {"workload": f"learned controller vs plain rule, nao {nao} naux {naux} "
                                   f"nocc {nocc}, {n_iter} iterations, eps 1e-2 -> 1e-8, "
                                   "per-64-aux-block scale 10^U(-4,0)",
-                      "training": "3 sequences nao 512 naux 2048 nocc 64 x 10 iterations",
+                      "training": "5 sequences x 10 iterations, nao 256 / 512 / 768 / 1024 / "
+                                  "1280, naux 4 nao, nocc nao / 8",
                       "fp64_below_level": below},
            "samples": int(x.shape[0]), "sample_seconds": t_samples, "train_seconds": t_train,
            "train_rms_decades": rms, "loss_first": float(losses[0]),

@@ -13,8 +13,14 @@ iteration the plain rule still names a reference count s_ref; the controller
 gives every block the count that keeps the predicted total error at or below
 that of s_ref everywhere, with the fewest digit products
 (df_controller_allocate).  Sampled blocks are recomputed in FP64
-(df_spot_check); a block whose error exceeds `margin` times its prediction
-sends the iteration back to the plain rule (uniform s_ref).
+(df_spot_check).  Their excess over the prediction, scaled up to all blocks
+(nblocks / samples times the summed excess), estimates how far the whole
+build overshoots its predicted error; when that estimate exceeds `margin`
+times the error budget (the predicted error of s_ref everywhere), the
+iteration is rebuilt by the plain rule (uniform s_ref).  The checks also
+feed back: a per-s correction (the largest log10 ratio of measured to
+predicted error seen at that s, decaying by `decay` per iteration) is added
+to the predictions before the next allocation.
 """
 import math
 
@@ -175,11 +181,15 @@ def evaluate(ctx, params, x, t, m):
 
 
 def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below_level=0,
-                   spot=2, margin=10.0, judge=False, seed=0):
+                   spot=2, margin=1.0, decay=0.9, judge=False, seed=0, s_refs=None):
     """The controlled sequence.  Per iteration: plain-rule reference count,
     features, prediction, per-block allocation, build, FP64 spot check (and
     fallback to the uniform reference count).  Returns per-iteration records
-    with the time, the per-block counts and their digit-product work."""
+    with the time, the per-block counts and their digit-product work.
+
+    s_refs: the reference counts to use instead of running the rule on this
+    sequence's own energies (e.g. those of a plain run, to compare the two at
+    the same reference accuracy in every iteration)."""
     import torch
     import dfinputs
     naux, nao = B.shape[0], B.shape[1]
@@ -194,9 +204,11 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
     K64 = torch.empty_like(b.K) if judge else None
     en64 = torch.empty_like(b.en) if judge else None
     level, e_prev, e_prev2 = 4, None, None
+    corr = np.zeros(8)  # per-s correction of the predictions (decades, >= 0)
     recs = []
     for k, C in enumerate(orbitals):
-        s_ref = binding.df_rule_slices(level, fp64_below_level)
+        corr *= decay
+        s_ref = binding.df_rule_slices(level, fp64_below_level) if s_refs is None else s_refs[k]
         ctx.df_density(C, occ, b.D)
         ev0.record()
         fallback = False
@@ -210,7 +222,7 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
             de = _rel_change(e_prev2, e_prev)
             feat = fs.features(C, b.D, k, len(orbitals), de, ACCURACY[level], s_ref)
             ctx.df_mlp_forward(params, feat, b.pred)
-            pred_h = b.pred.cpu().numpy()
+            pred_h = b.pred.cpu().numpy() + corr[None, :].astype(np.float32)
             sb = binding.df_controller_allocate(pred_h, s_ref)
             ctx.df_set_block_precision(sb)
             ctx.ensure_workspace(naux, nao, nocc)
@@ -222,10 +234,16 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
                 if kfro > 0:
                     ctx.df_spot_check(B, C, occ, kfro, blocks, spot_err[:len(blocks)])
                     se = spot_err[:len(blocks)].cpu().numpy()
+                    err_pred = np.minimum.accumulate(10.0 ** pred_h.astype(np.float64), axis=1)
+                    budget = float(err_pred[:, s_ref - 1].sum())
+                    excess = sum(max(0.0, float(se[i]) - float(err_pred[blk, sb[blk] - 1]))
+                                 for i, blk in enumerate(blocks))
+                    if nb / len(blocks) * excess > margin * budget:
+                        fallback = True
                     for i, blk in enumerate(blocks):
-                        lim = margin * 10.0 ** float(np.min(pred_h[blk, :sb[blk]]))
-                        if se[i] > lim and se[i] > 1e-16:
-                            fallback = True
+                        if se[i] > 0:
+                            r = math.log10(float(se[i]) / float(err_pred[blk, sb[blk] - 1]))
+                            corr[sb[blk] - 1] = max(corr[sb[blk] - 1], r)
             if fallback:
                 sb = [s_ref] * nb
                 ctx.df_set_block_precision(sb)
@@ -235,6 +253,7 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
         ms = ev0.elapsed_time(ev1)
         fs.after_build(b.D, b.K)
         rec = dict(iteration=k, level=level, s_ref=s_ref, slices=list(sb), fallback=fallback,
+                   correction=[round(float(v), 3) for v in corr],
                    work=int(sum(s * (s + 1) // 2 for s in sb)),
                    work_ref=int(nb * s_ref * (s_ref + 1) // 2), energy=e_now, ms=ms,
                    err_bound=float(b.eb.cpu()[0]))
