@@ -331,7 +331,7 @@ __device__ __forceinline__ void lower_tile(int idx, int& t1, int& t2) {
 // step's panels are prefetched into registers while the current step runs.
 // ---------------------------------------------------------------------------
 template <int S>
-__global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
+__global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
                                                 const int32_t* __restrict__ F, int nb, int nao,
                                                 int nao_pad, int kbp, int groups,
                                                 double* __restrict__ Kp) {
@@ -344,51 +344,45 @@ __global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
   const int grp = (int)(lid / ntile);
   int t1, t2;
   lower_tile((int)(lid - grp * ntile), t1, t2);
-  const bool diag = t1 == t2;
   const int b_lo = (int)((int64_t)grp * nb / groups);
   const int b_hi = (int)((int64_t)(grp + 1) * nb / groups);
+  // 8 waves, each a 32 x 16 piece of the 64 x 64 tile (two row fragments, one
+  // column fragment): small enough per wave for two waves per SIMD.
   const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int wr = (w >> 2) * 32, wc = (w & 3) * 16;
   const int64_t plane = (int64_t)nb * nao_pad * kbp;
   const int ksteps = kbp >> 6;
-  // loader: thread t moves row t/4, 16-byte part t%4 of every plane of both panels
-  const int lrow = t >> 2, lpart = t & 3;
-  const int8_t* srcA = Xd + (int64_t)(t1 * 64 + lrow) * kbp + lpart * 16;
-  const int8_t* srcB = Xd + (int64_t)(t2 * 64 + lrow) * kbp + lpart * 16;
-  const int ldst = lrow * ROW + swz(lrow, lpart);
-  i32x4 preA[S], preB[S];
+  // loader: threads 0..255 move the row panel (tile row t1), 256..511 the column
+  // panel (t2); thread u moves row u/4, 16-byte part u%4 of every plane
+  const int panel = t >> 8, u = t & 255, lrow = u >> 2, lpart = u & 3;
+  const int8_t* src = Xd + (int64_t)((panel ? t2 : t1) * 64 + lrow) * kbp + lpart * 16;
+  const int ldst = panel * S * 64 * ROW + lrow * ROW + swz(lrow, lpart);
+  i32x4 pre[S];
 #define DFJK_K_LOAD_STEP(BB, K0)                                                               \
   {                                                                                            \
     const int64_t off_ = (int64_t)(BB) * nao_pad * kbp + (K0);                                 \
     _Pragma("unroll") for (int a = 0; a < S; ++a)                                              \
-      preA[a] = *reinterpret_cast<const i32x4*>(srcA + a * plane + off_);                      \
-    _Pragma("unroll") for (int a = 0; a < S; ++a)                                              \
-      preB[a] = diag ? preA[a] : *reinterpret_cast<const i32x4*>(srcB + a * plane + off_);     \
+      pre[a] = *reinterpret_cast<const i32x4*>(src + a * plane + off_);                        \
   }
 
-  double kacc[2][2][4];
+  double kacc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) kacc[i][j][r] = 0.0;
+    for (int r = 0; r < 4; ++r) kacc[i][r] = 0.0;
 
   if (b_lo < b_hi) DFJK_K_LOAD_STEP(b_lo, 0)
   for (int b = b_lo; b < b_hi; ++b) {
-    i32x4 acc[S][2][2];
+    i32x4 acc[S][2];
 #pragma unroll
     for (int g = 0; g < S; ++g)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[g][i][j] = i32x4{0, 0, 0, 0};
+      for (int i = 0; i < 2; ++i) acc[g][i] = i32x4{0, 0, 0, 0};
     for (int ks = 0; ks < ksteps; ++ks) {
       __syncthreads();
 #pragma unroll
-      for (int a = 0; a < S; ++a) *reinterpret_cast<i32x4*>(&Ls[0][a][0][0] + ldst) = preA[a];
-#pragma unroll
-      for (int a = 0; a < S; ++a) *reinterpret_cast<i32x4*>(&Ls[1][a][0][0] + ldst) = preB[a];
+      for (int a = 0; a < S; ++a)
+        *reinterpret_cast<i32x4*>(&Ls[0][0][0][0] + ldst + a * 64 * ROW) = pre[a];
       __syncthreads();
       {
         const bool last = ks + 1 == ksteps;
@@ -396,13 +390,10 @@ __global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
         const int nk_ = last ? 0 : (ks + 1) * 64;
         if (nb_ < b_hi) DFJK_K_LOAD_STEP(nb_, nk_)
       }
-      i32x4 bf[S][2];
+      i32x4 bf[S];
 #pragma unroll
       for (int bb = 0; bb < S; ++bb)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          bf[bb][j] = *reinterpret_cast<const i32x4*>(
-              &Ls[1][bb][wc + j * 16 + r16][swz(wc + j * 16 + r16, q)]);
+        bf[bb] = *reinterpret_cast<const i32x4*>(&Ls[1][bb][wc + r16][swz(wc + r16, q)]);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         i32x4 af[S];
@@ -413,42 +404,33 @@ __global__ __launch_bounds__(256) void k_k_int8(const int8_t* __restrict__ Xd,
         for (int a = 0; a < S; ++a)
 #pragma unroll
           for (int bb = 0; bb < S - a; ++bb)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-              acc[a + bb][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[bb][j],
-                                                                      acc[a + bb][i][j], 0, 0, 0);
+            acc[a + bb][i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[bb], acc[a + bb][i], 0, 0, 0);
       }
     }
     // end of aux block b: recombine into the FP64 partial sum
     const int32_t* Fb = F + (int64_t)b * nao_pad;
+    const int fn = Fb[t2 * 64 + wc + r16];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int fn = Fb[t2 * 64 + wc + j * 16 + r16];
+      for (int r = 0; r < 4; ++r) {
+        const int base = Fb[t1 * 64 + wr + i * 16 + q * 4 + r] + fn + 4;
+        double z = 0.0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int base = Fb[t1 * 64 + wr + i * 16 + q * 4 + r] + fn + 4;
-          double z = 0.0;
-#pragma unroll
-          for (int g = S + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][i][j][r], base - 8 * g);
-          kacc[i][j][r] += z;
-        }
+        for (int g = S + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][i][r], base - 8 * g);
+        kacc[i][r] += z;
       }
   }
 
 #undef DFJK_K_LOAD_STEP
   double* out = Kp + (int64_t)grp * nao * nao;
+  const int nu = t2 * 64 + wc + r16;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int nu = t2 * 64 + wc + j * 16 + r16;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int mu = t1 * 64 + wr + i * 16 + q * 4 + r;
-        if (mu < nao && nu < nao) out[(int64_t)mu * nao + nu] = kacc[i][j][r];
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int mu = t1 * 64 + wr + i * 16 + q * 4 + r;
+      if (mu < nao && nu < nao) out[(int64_t)mu * nao + nu] = kacc[i][r];
     }
 }
 
@@ -591,7 +573,7 @@ hipError_t launch_k_int8(hipStream_t st, int s, const int8_t* Xd, const int32_t*
   const int nt = nao_pad / 64;
   const dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)groups);
 #define DFJK_K(SS) \
-  hipLaunchKernelGGL((k_k_int8<SS>), grid, dim3(256), 0, st, Xd, F, nb, nao, nao_pad, kbp, groups, Kp)
+  hipLaunchKernelGGL((k_k_int8<SS>), grid, dim3(512), 0, st, Xd, F, nb, nao, nao_pad, kbp, groups, Kp)
   switch (s) {
     case 1: DFJK_K(1); break;
     case 2: DFJK_K(2); break;
