@@ -76,7 +76,23 @@ __global__ __launch_bounds__(256) void k_j_tri(const double* __restrict__ B, int
     double a[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) a[j] = 0.0;
-    for (int64_t P = p_lo; P < p_hi; ++P) {
+    // four aux indices per step: 4 EPT independent loads in flight per lane
+    int64_t P = p_lo;
+    for (; P + 4 <= p_hi; P += 4) {
+      double bv[4][EPT];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) bv[u][j] = rd[j] ? B[(P + u) * nn + off[j]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double r = rho[P + u];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          if (rd[j]) a[j] = fma(r, bv[u][j], a[j]);
+      }
+    }
+    for (; P < p_hi; ++P) {
       const double r = rho[P];
       const double* bp = B + P * nn;
 #pragma unroll
