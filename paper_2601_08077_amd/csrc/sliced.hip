@@ -78,7 +78,14 @@ __global__ __launch_bounds__(256 * NH) void k_x_dig(
   constexpr int NF = NFW * NH, NT = 16 * NF, ROW = 64, NTHR = 256 * NH;
   constexpr int CUNITS = S * NT * 4;
   constexpr int CPER = (CUNITS + NTHR - 1) / NTHR;
-  __shared__ __attribute__((aligned(16))) int8_t Cs[S][NT][ROW];
+  // C digits in two LDS stages (one barrier per chunk); the A and D fragments
+  // come straight from global memory, PF chunks ahead in registers
+  // (measured per s: the deeper pipeline pays for 4 <= s <= 7; at s = 3 the
+  // extra registers cost more occupancy than they hide, at s = 8 they spill)
+  constexpr int NBUF = (S >= 4 && S <= 7) ? 2 : 1;
+  constexpr int PF = S == 4 ? 2 : 1;
+  constexpr bool DPF = S >= 4 && S <= 6;  // D fragments prefetched too
+  __shared__ __attribute__((aligned(16))) int8_t Cs[NBUF][S][NT][ROW];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
   const int wr = w & 3, half = w >> 2;
   int64_t m0 = (int64_t)blockIdx.x * 64;
@@ -117,57 +124,139 @@ __global__ __launch_bounds__(256 * NH) void k_x_dig(
 #pragma unroll
   for (int g = 0; g < S; ++g) rdi[g] = 0;
 
-  i32x4 af[S], cpre[CPER];
-#define DFJK_XD_LOAD(CC)                                                                 \
-  {                                                                                      \
-    const int kb = (CC) * 64;                                                            \
-    _Pragma("unroll") for (int a = 0; a < S; ++a) af[a] =                                \
-        *reinterpret_cast<const i32x4*>(asrc + a * bplane + kb);                         \
-    _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                   \
-      if (t + NTHR * i < CUNITS) cpre[i] = *reinterpret_cast<const i32x4*>(csrc[i] + kb); \
-    }                                                                                    \
+  i32x4 af[PF][S], dp[PF][S], cpre[CPER];
+#define DFJK_XD_LOADA(SLOT, CC)                                                            \
+  {                                                                                        \
+    const int kb = (CC) * 64;                                                              \
+    _Pragma("unroll") for (int a = 0; a < S; ++a) af[SLOT][a] =                            \
+        *reinterpret_cast<const i32x4*>(asrc + a * bplane + kb);                           \
+    if (DPF && want_rd) {                                                                  \
+      _Pragma("unroll") for (int b = 0; b < S; ++b) dp[SLOT][b] =                          \
+          *reinterpret_cast<const i32x4*>(dsrc + b * dplane + kb);                         \
+    }                                                                                      \
   }
-  DFJK_XD_LOAD(0)
+#define DFJK_XD_LOADC(CC)                                                                  \
+  {                                                                                        \
+    const int kb = (CC) * 64;                                                              \
+    _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                     \
+      if (t + NTHR * i < CUNITS) cpre[i] = *reinterpret_cast<const i32x4*>(csrc[i] + kb);  \
+    }                                                                                      \
+  }
+#define DFJK_XD_STOREC(BUF)                                                                \
+  {                                                                                        \
+    _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                     \
+      if (t + NTHR * i < CUNITS)                                                           \
+        *reinterpret_cast<i32x4*>(&Cs[BUF][0][0][0] + cdst[i]) = cpre[i];                  \
+    }                                                                                      \
+  }
+  if constexpr (NBUF == 2) {
+  DFJK_XD_LOADA(0, 0)
+  DFJK_XD_LOADC(0)
+  DFJK_XD_STOREC(0)
+  if (PF == 2 && nch > 1) DFJK_XD_LOADA(PF - 1, 1)
+  if (nch > 1) DFJK_XD_LOADC(1)
+  __syncthreads();
   for (int c = 0; c < nch; ++c) {
-    const int k0 = c * 64;
-    __syncthreads();
+    const int buf = c & 1;
+    if (c + 1 < nch) DFJK_XD_STOREC(buf ^ 1)  // stage buf ^ 1 was last read before the barrier
+    i32x4 acur[S], dcur[S];
 #pragma unroll
-    for (int i = 0; i < CPER; ++i)
-      if (t + NTHR * i < CUNITS) *reinterpret_cast<i32x4*>(&Cs[0][0][0] + cdst[i]) = cpre[i];
-    __syncthreads();
-    i32x4 acur[S];
+    for (int a = 0; a < S; ++a) {
+      acur[a] = af[0][a];
+      if (DPF) dcur[a] = dp[0][a];
+    }
+    if (!DPF && want_rd) {
 #pragma unroll
-    for (int a = 0; a < S; ++a) acur[a] = af[a];
-    if (c + 1 < nch) DFJK_XD_LOAD(c + 1)
+      for (int b = 0; b < S; ++b)
+        dcur[b] = *reinterpret_cast<const i32x4*>(dsrc + b * dplane + c * 64);
+    }
+    if (PF == 2) {
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        af[0][a] = af[PF - 1][a];
+        if (DPF) dp[0][a] = dp[PF - 1][a];
+      }
+      if (c + 2 < nch) DFJK_XD_LOADA(PF - 1, c + 2)
+    } else if (c + 1 < nch) {
+      DFJK_XD_LOADA(0, c + 1)
+    }
+    if (c + 2 < nch) DFJK_XD_LOADC(c + 2)
     if (want_rd) {
-      i32x4 dd[S];
-#pragma unroll
-      for (int b = 0; b < S; ++b) dd[b] = *reinterpret_cast<const i32x4*>(dsrc + b * dplane + k0);
 #pragma unroll
       for (int a = 0; a < S; ++a)
 #pragma unroll
         for (int b = 0; b < S - a; ++b) {
           int v = rdi[a + b];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) v = __builtin_amdgcn_sdot4(acur[a][j], dd[b][j], v, false);
+          for (int j = 0; j < 4; ++j) v = __builtin_amdgcn_sdot4(acur[a][j], dcur[b][j], v, false);
           rdi[a + b] = v;
         }
     }
 #pragma unroll
     for (int f = 0; f < NFW; ++f) {
+      const int col = (half * NFW + f) * 16 + r16;
       i32x4 bf[S];
 #pragma unroll
       for (int b = 0; b < S; ++b)
-        bf[b] = *reinterpret_cast<const i32x4*>(
-            &Cs[b][(half * NFW + f) * 16 + r16][swz((half * NFW + f) * 16 + r16, q)]);
+        bf[b] = *reinterpret_cast<const i32x4*>(&Cs[buf][b][col][swz(col, q)]);
 #pragma unroll
       for (int a = 0; a < S; ++a)
 #pragma unroll
         for (int b = 0; b < S - a; ++b)
           acc[a + b][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(acur[a], bf[b], acc[a + b][f], 0, 0, 0);
     }
+    __syncthreads();
   }
-#undef DFJK_XD_LOAD
+  } else {
+    // one LDS stage: store, barrier, multiply, barrier
+    DFJK_XD_LOADA(0, 0)
+    DFJK_XD_LOADC(0)
+    for (int c = 0; c < nch; ++c) {
+      const int buf = 0;
+      __syncthreads();
+      DFJK_XD_STOREC(0)
+      __syncthreads();
+      i32x4 acur[S], dcur[S];
+#pragma unroll
+      for (int a = 0; a < S; ++a) acur[a] = af[0][a];
+      if (c + 1 < nch) {
+        DFJK_XD_LOADA(0, c + 1)
+        DFJK_XD_LOADC(c + 1)
+      }
+      if (want_rd) {
+#pragma unroll
+        for (int b = 0; b < S; ++b)
+          dcur[b] = *reinterpret_cast<const i32x4*>(dsrc + b * dplane + c * 64);
+      }
+    if (want_rd) {
+#pragma unroll
+      for (int a = 0; a < S; ++a)
+#pragma unroll
+        for (int b = 0; b < S - a; ++b) {
+          int v = rdi[a + b];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v = __builtin_amdgcn_sdot4(acur[a][j], dcur[b][j], v, false);
+          rdi[a + b] = v;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < NFW; ++f) {
+      const int col = (half * NFW + f) * 16 + r16;
+      i32x4 bf[S];
+#pragma unroll
+      for (int b = 0; b < S; ++b)
+        bf[b] = *reinterpret_cast<const i32x4*>(&Cs[buf][b][col][swz(col, q)]);
+#pragma unroll
+      for (int a = 0; a < S; ++a)
+#pragma unroll
+        for (int b = 0; b < S - a; ++b)
+          acc[a + b][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(acur[a], bf[b], acc[a + b][f], 0, 0, 0);
+    }
+    }
+  }
+#undef DFJK_XD_STOREC
+#undef DFJK_XD_LOADC
+#undef DFJK_XD_LOADA
 
   if (want_rd) {
     // exact sums over the four lane groups of the row, then its recombination
