@@ -305,24 +305,45 @@ __global__ __launch_bounds__(256 * NH) void k_x_dig(
 
 // rho_P = sum_mu rowdot[P nao + mu] with mu ascending (one thread per P), and
 // the bound on |rho_P - rho_hat_P|: the emulated row dots (nao terms each,
-// exponents e_B + g) plus the nao - 1 roundings of the mu sum.
-__global__ void k_rho_seq(const double* __restrict__ rowdot, const int32_t* __restrict__ b_exp,
-                          const int32_t* __restrict__ d_exp, int64_t naux, int nao,
-                          double kap_row, double kap_sum, double* __restrict__ rho,
-                          double* __restrict__ drho) {
-  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (P >= naux) return;
-  const double* r = rowdot + P * nao;
-  const int32_t* e = b_exp + P * nao;
+// exponents e_B + g) plus the nao - 1 roundings of the mu sum.  A workgroup
+// takes 64 consecutive P; 64 x 64 tiles of the row dots and exponents are read
+// coalesced into LDS and each of 64 threads walks its row of the tile.
+__global__ __launch_bounds__(256) void k_rho_seq(const double* __restrict__ rowdot,
+                                                 const int32_t* __restrict__ b_exp,
+                                                 const int32_t* __restrict__ d_exp, int64_t naux,
+                                                 int nao, double kap_row, double kap_sum,
+                                                 double* __restrict__ rho,
+                                                 double* __restrict__ drho) {
+  __shared__ double tr[64][65];
+  __shared__ int te[64][65];
+  const int t = threadIdx.x;
+  const int64_t P0 = (int64_t)blockIdx.x * 64;
   double a = 0.0, sabs = 0.0, srow = 0.0;
-  for (int mu = 0; mu < nao; ++mu) {
-    const double v = r[mu];
-    a += v;
-    sabs += fabs(v);
-    srow += ldexp(1.0, e[mu] + d_exp[mu]);
+  for (int mu0 = 0; mu0 < nao; mu0 += 64) {
+    __syncthreads();
+    for (int e = t; e < 64 * 64; e += 256) {
+      const int pl = e >> 6, ml = e & 63;
+      const int64_t P = P0 + pl;
+      const int mu = mu0 + ml;
+      const bool ok = P < naux && mu < nao;
+      tr[pl][ml] = ok ? rowdot[P * nao + mu] : 0.0;
+      te[pl][ml] = ok ? b_exp[P * nao + mu] + d_exp[mu] : 0;
+    }
+    __syncthreads();
+    if (t < 64) {
+      const int mend = nao - mu0 < 64 ? nao - mu0 : 64;
+      for (int ml = 0; ml < mend; ++ml) {
+        const double v = tr[t][ml];
+        a += v;
+        sabs += fabs(v);
+        srow += ldexp(1.0, te[t][ml]);
+      }
+    }
   }
-  rho[P] = a;
-  drho[P] = (double)nao * kap_row * srow + kap_sum * sabs;
+  if (t < 64 && P0 + t < naux) {
+    rho[P0 + t] = a;
+    drho[P0 + t] = (double)nao * kap_row * srow + kap_sum * sabs;
+  }
 }
 
 // For one mu: w[P] = rho_P 2^e[P, mu]; h_mu = exponent of max_P |w|; the digit
@@ -540,7 +561,7 @@ hipError_t launch_x_dig(hipStream_t st, int s, const int8_t* Bd, int64_t bplane,
 hipError_t launch_rho_seq(hipStream_t st, const double* rowdot, const int32_t* b_exp,
                           const int32_t* d_exp, int64_t naux, int nao, double kap_row,
                           double kap_sum, double* rho, double* drho) {
-  hipLaunchKernelGGL(k_rho_seq, dim3((unsigned)((naux + 255) / 256)), dim3(256), 0, st, rowdot,
+  hipLaunchKernelGGL(k_rho_seq, dim3((unsigned)((naux + 63) / 64)), dim3(256), 0, st, rowdot,
                      b_exp, d_exp, naux, nao, kap_row, kap_sum, rho, drho);
   return hipGetLastError();
 }
