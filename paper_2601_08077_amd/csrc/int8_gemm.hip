@@ -26,16 +26,18 @@ __device__ __forceinline__ uint32_t pack4(uint64_t w0, uint64_t w1, uint64_t w2,
 }
 
 // ---------------------------------------------------------------------------
-// X = B C.  Workgroup: 8 waves, tile 64 rows (P, mu) x 16*NF columns i.  Waves
-// w and w + 4 own rows 16 (w % 4) .. + 15 and split the columns in halves.
-// Lane l of either wave reads row (l & 15) of B and half of the 16 k "slots"
-// of lane group q = l >> 4 (slot 2 j + h of group q holds k = 8 j + 2 q + h;
-// the C digit planes are stored in the same order), slices its 8 values in
-// registers and writes their digits to the LDS A tile; the C digits of the
-// chunk are staged in LDS as well.  The next chunk of B (and D) is prefetched
-// into registers while the current one is multiplied.  Optionally the row
-// dots sum_nu B[P][mu][nu] D[mu][nu] (rho, Eq. 3) are formed from the same B
-// values.
+// X = B C.  Workgroup: 8 waves, tile 64 rows (P, mu) x 16*NF columns i.  For
+// the MFMAs, waves w and w + 4 own rows 16 (w % 4) .. + 15 and split the
+// columns in halves.  For loading and slicing, wave w takes rows 8 w .. 8 w + 7
+// of the tile, eight lanes per row: lane m = l & 7 of a row reads k = 16 j +
+// 2 m + {0, 1} (j = 0..3) of each 64-wide sub-chunk, so that every load
+// instruction covers whole 128-byte lines, slices its 8 values in registers
+// and writes their digits as 8 consecutive bytes of the LDS A row: MFMA slot
+// 8 (m & 1) + 2 j + h of lane group m >> 1 holds k = 16 j + 2 m + h (the C
+// digit planes are stored in the same order).  The C digits of the chunk are
+// staged in LDS as well.  The next chunk of B (and D) is prefetched into
+// registers while the current one is multiplied.  Optionally the row dots
+// sum_nu B[P][mu][nu] D[mu][nu] (rho, Eq. 3) are formed from the same B values.
 // X layout 0: X[row][i]; layout 1 (blocked): X_b rows, element
 // ((b nao + mu) pblk + P - P0) nocc + i.
 // ---------------------------------------------------------------------------
@@ -56,10 +58,10 @@ __global__ __launch_bounds__(512) void k_x_int8(
   constexpr int NBUF = (KSUB == 1 && 2 * S * (64 + NT) * ROW + 1024 <= 160 * 1024) ? 2 : 1;
   __shared__ __attribute__((aligned(16))) int8_t As[NBUF][S][64][ROW];
   __shared__ __attribute__((aligned(16))) int8_t Cs[NBUF][S][NT][ROW];
-  __shared__ double rdx[4][16];
 
   const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
   const int wrow = w & 3, half = w >> 2;  // waves w and w + 4 share 16 rows
+  const int lrow = 8 * w + (l >> 3), lm = l & 7;  // loader: tile row, lane within row
   // Workgroups that run together share the basis-row tile mu0..mu0+63 (and so
   // the same rows of D, which stay in L2) and differ in the aux index P.
   int64_t m0 = (int64_t)blockIdx.x * 64;
@@ -69,18 +71,15 @@ __global__ __launch_bounds__(512) void k_x_int8(
     m0 = P * nao + mt * 64;
   }
   const int n0 = blockIdx.y * NT;
-  const int64_t arow = m0 + wrow * 16 + r16;
+  // Rows past M read row 0 (in bounds); their digits and sums are discarded.
+  const int64_t arow = m0 + lrow;
   const bool aok = arow < M;
-  // In every 64-wide k sub-chunk each lane slices 8 of the 16 k slots of its
-  // lane group q: half h of the slots, k = 8 j + 2 q + {0, 1} for
-  // j = 4 h .. 4 h + 3.  Rows past M read row 0 (in bounds); their digits and
-  // sums are discarded.
-  const double* brow = B + (aok ? arow : 0) * (int64_t)K + 2 * q + 32 * half;
+  const double* brow = B + (aok ? arow : 0) * (int64_t)K + 2 * lm;
   const int e_a = aok ? b_exp[arow] : 0;
   const bool want_rd = D != nullptr;
-  const double* drow = (want_rd ? D : B) + (aok ? (arow % nao) : 0) * (int64_t)K + 2 * q + 32 * half;
+  const double* drow = (want_rd ? D : B) + (aok ? (arow % nao) : 0) * (int64_t)K + 2 * lm;
   const int nch = (K + KC - 1) / KC;
-  int8_t* adst = &As[0][0][wrow * 16 + r16][swz(wrow * 16 + r16, q) + half * 8];
+  int8_t* adst = &As[0][0][lrow][swz(lrow, lm >> 1) + (lm & 1) * 8];
   // Screened B: only the KC-wide nu chunks that meet a kept block in some row
   // of this tile are visited (the rest of the tile is zero).
   const unsigned long long live = cmask ? tile_chunks<KSUB>(cmask, m0, M, nao, w, l) : 0ull;
@@ -112,14 +111,14 @@ __global__ __launch_bounds__(512) void k_x_int8(
     const int kb0 = (CC) * KC;                                                             \
     if (FULLK) {                                                                           \
       _Pragma("unroll") for (int j = 0; j < NV / 2; ++j) {                                 \
-        const int off = kb0 + 64 * (j >> 2) + 8 * (j & 3);                                 \
+        const int off = kb0 + 64 * (j >> 2) + 16 * (j & 3);                                \
         const double2 p = *reinterpret_cast<const double2*>(brow + off);                   \
         v[2 * j] = p.x;                                                                    \
         v[2 * j + 1] = p.y;                                                                \
       }                                                                                    \
       if (want_rd) {                                                                       \
         _Pragma("unroll") for (int j = 0; j < NV / 2; ++j) {                               \
-          const int off = kb0 + 64 * (j >> 2) + 8 * (j & 3);                               \
+          const int off = kb0 + 64 * (j >> 2) + 16 * (j & 3);                              \
           const double2 p = *reinterpret_cast<const double2*>(drow + off);                 \
           dv[2 * j] = p.x;                                                                 \
           dv[2 * j + 1] = p.y;                                                             \
@@ -127,8 +126,8 @@ __global__ __launch_bounds__(512) void k_x_int8(
       }                                                                                    \
     } else {                                                                               \
       _Pragma("unroll") for (int j = 0; j < NV; ++j) {                                     \
-        const int off = kb0 + 64 * (j >> 3) + 8 * ((j >> 1) & 3) + (j & 1);               \
-        const int kk = off + 2 * q + 32 * half;                                            \
+        const int off = kb0 + 64 * (j >> 3) + 16 * ((j >> 1) & 3) + (j & 1);              \
+        const int kk = off + 2 * lm;                                                       \
         v[j] = kk < K ? brow[off] : 0.0;                                                   \
         dv[j] = (want_rd && kk < K) ? drow[off] : 0.0;                                     \
       }                                                                                    \
@@ -218,12 +217,11 @@ __global__ __launch_bounds__(512) void k_x_int8(
 #undef DFJK_X_LOAD
 
   if (rowdot) {
-    // row dot = (lane groups of half 0) + (lane groups of half 1), fixed order
-    rd += __shfl_xor(rd, 16);
-    rd += __shfl_xor(rd, 32);
-    if (half == 1 && q == 0) rdx[wrow][r16] = rd;
-    __syncthreads();
-    if (half == 0 && q == 0 && aok && blockIdx.y == 0) rowdot[arow] = rd + rdx[wrow][r16];
+    // row dot = sum over the eight lanes of the row, fixed order
+    rd += __shfl_xor(rd, 1);
+    rd += __shfl_xor(rd, 2);
+    rd += __shfl_xor(rd, 4);
+    if (lm == 0 && aok && blockIdx.y == 0) rowdot[arow] = rd;
   }
 
   // Recombination, X store, and the per-(block, mu) running max of |X|.

@@ -63,8 +63,9 @@ __global__ void k_slice_rows(const double* __restrict__ A, int64_t rows, int64_t
 }
 
 // Digit planes of C^T in the right-operand layout of the INT8 X product:
-// dC[a][i][p] with p = 64 c + 16 q + (2 j + h) holding k = 64 c + 8 j + 2 q + h
-// (the order in which the B-tile loader hands k to its four lane groups), or
+// dC[a][i][p] with p = 64 c + 16 q + 8 b + 2 j + h holding
+// k = 64 c + 16 j + 4 q + 2 b + h (the order in which the B-tile loader's
+// eight lanes per row place their values in the four MFMA lane groups), or
 // p = k when `natural` is set (X from B digit planes).
 __global__ void k_slice_c(const double* __restrict__ C, int64_t nao, int64_t nocc, int s,
                           const int32_t* __restrict__ f, int ncp, int kp, int natural,
@@ -74,9 +75,8 @@ __global__ void k_slice_c(const double* __restrict__ C, int64_t nao, int64_t noc
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx / kp);
     const int p = (int)(idx - (int64_t)i * kp);
-    const int c = p >> 6, q = (p >> 4) & 3, slot = p & 15;
-    const int j = slot >> 1, h = slot & 1;
-    const int64_t k = natural ? p : (int64_t)c * 64 + 8 * j + 2 * q + h;
+    const int c = p >> 6, q = (p >> 4) & 3, b = (p >> 3) & 1, j = (p >> 1) & 3, h = p & 1;
+    const int64_t k = natural ? p : (int64_t)c * 64 + 16 * j + 4 * q + 2 * b + h;
     uint64_t w = 0;
     if (i < nocc && k < nao) w = digit_word(C[k * nocc + i], f[i]);
     for (int a = 0; a < s; ++a) dC[(int64_t)a * n + idx] = (int8_t)digit_byte(w, a + 1);
