@@ -19,6 +19,15 @@
 namespace dfjk {
 namespace {
 
+// 16 bytes per lane from a buffer resource (byte offset voff + soff) straight
+// into LDS: lane i of the wave writes bytes 16 i .. 16 i + 15 after the
+// wave-uniform LDS address lds_dst.  Completion is counted by vmcnt.
+__device__ __forceinline__ void copy16_to_lds(__amdgpu_buffer_rsrc_t r, void* lds_dst, int voff,
+                                              int soff) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds_dst, 16,
+                                           voff, soff, 0, 0);
+}
+
 __device__ __forceinline__ uint32_t pack4(uint64_t w0, uint64_t w1, uint64_t w2, uint64_t w3,
                                           int k) {
   return digit_byte(w0, k) | (digit_byte(w1, k) << 8) | (digit_byte(w2, k) << 16) |
@@ -57,7 +66,15 @@ __global__ __launch_bounds__(512) void k_x_int8(
   // written while chunk c is multiplied, one barrier per chunk.
   constexpr int NBUF = (KSUB == 1 && 2 * S * (64 + NT) * ROW + 1024 <= 160 * 1024) ? 2 : 1;
   __shared__ __attribute__((aligned(16))) int8_t As[NBUF][S][64][ROW];
-  __shared__ __attribute__((aligned(16))) int8_t Cs[NBUF][S][NT][ROW];
+  // The two C stages are separate arrays, so that the compiler can tell the
+  // stage being copied into from the one being read.  With two stages each
+  // has 16 spare rows (1 KB) at its end: the landing block of the copies of
+  // waves that have no block left in a chunk (every wave issues the same
+  // number of copies; never read).
+  constexpr int CPAD = NBUF == 2 && CUNITS % 512 ? 16 : 0;
+  __shared__ __attribute__((aligned(16))) int8_t Cs0[S * NT + CPAD][ROW];
+  __shared__ __attribute__((aligned(16))) int8_t Cs1[NBUF == 2 ? S * NT + CPAD : 1][ROW];
+#define DFJK_CSB(BUF) ((BUF) ? Cs1 : Cs0)
 
   const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
   const int wrow = w & 3, half = w >> 2;  // waves w and w + 4 share 16 rows
@@ -97,6 +114,27 @@ __global__ __launch_bounds__(512) void k_x_int8(
     cdst[i] = (a * NT + col) * ROW + (part >> 2) * 64 + swz(col, part & 3);
   }
 
+  // With two LDS stages the C digits go straight from memory to LDS (one
+  // 1 KB block of 16 columns of one plane per wave instruction; lane i lands
+  // at byte 16 i of the block, so it fetches the unit that the row swizzle
+  // puts there).
+  // The copies are buffer loads (byte offsets from a resource over the S
+  // digit planes of C, bounds-checked by the hardware).
+  constexpr int CINS = CUNITS / 64, CIW = (CINS + 7) / 8;
+  const __amdgpu_buffer_rsrc_t crsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<int8_t*>(dC), (short)0, S * ncp * kp, 0x00020000);
+  int coff[NBUF == 2 ? CIW : 1];
+  if constexpr (NBUF == 2) {
+#pragma unroll
+    for (int j = 0; j < CIW; ++j) {
+      const int ins = w + 8 * j;
+      const int u0 = (ins < CINS ? ins : 0) * 64;
+      const int a = u0 / (NT * 4 * KSUB), col0 = (u0 - a * NT * 4 * KSUB) / (4 * KSUB);
+      const int col = col0 + (l >> 2), part = (l & 3) ^ ((col >> 1) & 3);
+      coff[j] = (a * ncp + n0 + col) * kp + part * 16;
+    }
+  }
+
   i32x4 acc[S][NFW];
 #pragma unroll
   for (int g = 0; g < S; ++g)
@@ -105,7 +143,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
   double rd = 0.0;
 
   double v[NV], dv[NV];
-  i32x4 cpre[CPER];
+  i32x4 cpre[NBUF == 1 ? CPER : 1];
 #define DFJK_X_LOAD(CC)                                                                    \
   {                                                                                        \
     const int kb0 = (CC) * KC;                                                             \
@@ -116,13 +154,13 @@ __global__ __launch_bounds__(512) void k_x_int8(
         v[2 * j] = p.x;                                                                    \
         v[2 * j + 1] = p.y;                                                                \
       }                                                                                    \
-      if (want_rd) {                                                                       \
-        _Pragma("unroll") for (int j = 0; j < NV / 2; ++j) {                               \
-          const int off = kb0 + 64 * (j >> 2) + 16 * (j & 3);                              \
-          const double2 p = *reinterpret_cast<const double2*>(drow + off);                 \
-          dv[2 * j] = p.x;                                                                 \
-          dv[2 * j + 1] = p.y;                                                             \
-        }                                                                                  \
+      /* D rows are read even when unused (drow then points into B), so that */           \
+      /* every step issues the same number of loads */                                      \
+      _Pragma("unroll") for (int j = 0; j < NV / 2; ++j) {                                 \
+        const int off = kb0 + 64 * (j >> 2) + 16 * (j & 3);                                \
+        const double2 p = *reinterpret_cast<const double2*>(drow + off);                   \
+        dv[2 * j] = p.x;                                                                   \
+        dv[2 * j + 1] = p.y;                                                               \
       }                                                                                    \
     } else {                                                                               \
       _Pragma("unroll") for (int j = 0; j < NV; ++j) {                                     \
@@ -132,18 +170,28 @@ __global__ __launch_bounds__(512) void k_x_int8(
         dv[j] = (want_rd && kk < K) ? drow[off] : 0.0;                                     \
       }                                                                                    \
     }                                                                                      \
-    _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                     \
-      if (t + 512 * i < CUNITS) cpre[i] = *reinterpret_cast<const i32x4*>(csrc[i] + kb0);  \
+    if constexpr (NBUF == 1) {                                                             \
+      _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                   \
+        if (t + 512 * i < CUNITS) cpre[i] = *reinterpret_cast<const i32x4*>(csrc[i] + kb0); \
+      }                                                                                    \
     }                                                                                      \
+  }
+  // C digits of chunk CC straight into LDS stage BUF (two-stage loop only).
+#define DFJK_X_CDMA(BUF, CC)                                                                \
+  _Pragma("unroll") for (int j = 0; j < CIW; ++j) {                                        \
+    const int ins = w + 8 * j;                                                             \
+    /* block ins: plane a, columns col0 .. col0 + 15 (spare rows past the last) */        \
+    const int row0 = ins < CINS ? (ins * 64) / 4 : S * NT;                                 \
+    int8_t* dst = &DFJK_CSB(BUF)[row0][0];                                                  \
+    copy16_to_lds(crsrc, dst, coff[j], (CC) * KC);                                         \
   }
 
   // Digits of the chunk whose B values and C digits sit in registers, into
   // LDS stage BUF (and its B.D row-dot terms into rd).
 #define DFJK_X_STAGE(BUF)                                                                       \
   {                                                                                             \
-    if (want_rd) {                                                                              \
-      _Pragma("unroll") for (int j = 0; j < NV; ++j) rd = fma(v[j], dv[j], rd);                 \
-    }                                                                                           \
+    /* row-dot terms (zeroed after the loop when there is no D) */                              \
+    _Pragma("unroll") for (int j = 0; j < NV; ++j) rd = fma(v[j], dv[j], rd);                   \
     _Pragma("unroll") for (int sub = 0; sub < KSUB; ++sub) {                                    \
       uint64_t wd[8];                                                                           \
       _Pragma("unroll") for (int j = 0; j < 8; ++j) wd[j] = digit_word(v[8 * sub + j], e_a);    \
@@ -152,9 +200,11 @@ __global__ __launch_bounds__(512) void k_x_int8(
             make_uint2(pack4(wd[0], wd[1], wd[2], wd[3], a + 1),                                \
                        pack4(wd[4], wd[5], wd[6], wd[7], a + 1));                               \
     }                                                                                           \
-    _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                          \
-      if (t + 512 * i < CUNITS)                                                                 \
-        *reinterpret_cast<i32x4*>(&Cs[BUF][0][0][0] + cdst[i]) = cpre[i];                       \
+    if constexpr (NBUF == 1) {                                                                  \
+      _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                        \
+        if (t + 512 * i < CUNITS)                                                               \
+          *reinterpret_cast<i32x4*>(&DFJK_CSB(BUF)[0][0] + cdst[i]) = cpre[i];                  \
+      }                                                                                         \
     }                                                                                           \
   }
   // MFMAs of the chunk held in LDS stage BUF.
@@ -167,7 +217,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
       const int col = (half * NFW + f) * 16 + r16;                                              \
       i32x4 bf[S];                                                                              \
       _Pragma("unroll") for (int b = 0; b < S; ++b) bf[b] =                                     \
-          *reinterpret_cast<const i32x4*>(&Cs[BUF][b][col][sub * 64 + swz(col, q)]);            \
+          *reinterpret_cast<const i32x4*>(&DFJK_CSB(BUF)[b * NT + col][sub * 64 + swz(col, q)]); \
       _Pragma("unroll") for (int a = 0; a < S; ++a)                                             \
         _Pragma("unroll") for (int b = 0; b < S - a; ++b) acc[a + b][f] =                       \
             __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a + b][f], 0, 0, 0);        \
@@ -184,22 +234,38 @@ __global__ __launch_bounds__(512) void k_x_int8(
     // one after, multiply the current one, one barrier.
     int cn = next_of(c);
     if (c >= 0) {
+      DFJK_X_CDMA(0, c)
       DFJK_X_LOAD(c)
       DFJK_X_STAGE(0)
     }
     if (cn >= 0) DFJK_X_LOAD(cn)
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's C digits have landed in LDS
     __syncthreads();
-    int buf = 0;
+    // One step with chunk c in stage BB: stage chunk cn's A digits into the
+    // other stage, issue the loads of chunk cnn, start the copy of chunk cn's
+    // C digits into the other stage (after the loads: the compiler waits for
+    // every pending copy before it reuses a register), multiply chunk c and
+    // meet at the barrier (which waits for this wave's copies and loads).
+#define DFJK_X_STEP(BB)                                                                         \
+  {                                                                                             \
+    const int cnn = next_of(cn);                                                                \
+    if (cn >= 0) DFJK_X_STAGE(1 - (BB))                                                         \
+    __builtin_amdgcn_sched_barrier(0);                                                          \
+    if (cnn >= 0) DFJK_X_LOAD(cnn)                                                              \
+    __builtin_amdgcn_sched_barrier(0);                                                          \
+    if (cn >= 0) DFJK_X_CDMA(1 - (BB), cn)                                                      \
+    __builtin_amdgcn_sched_barrier(0);                                                          \
+    DFJK_X_MMA(BB)                                                                              \
+    __syncthreads();                                                                            \
+    c = cn;                                                                                     \
+    cn = cnn;                                                                                   \
+  }
     while (c >= 0) {
-      const int cnn = next_of(cn);
-      if (cn >= 0) DFJK_X_STAGE(buf ^ 1)
-      if (cnn >= 0) DFJK_X_LOAD(cnn)
-      DFJK_X_MMA(buf)
-      __syncthreads();  // stage buf may be overwritten, stage buf ^ 1 is complete
-      buf ^= 1;
-      c = cn;
-      cn = cnn;
+      DFJK_X_STEP(0)
+      if (c < 0) break;
+      DFJK_X_STEP(1)
     }
+#undef DFJK_X_STEP
   } else {
     if (c >= 0) DFJK_X_LOAD(c)
     while (c >= 0) {
@@ -212,9 +278,12 @@ __global__ __launch_bounds__(512) void k_x_int8(
       c = cn;
     }
   }
+  if (!want_rd) rd = 0.0;
 #undef DFJK_X_MMA
 #undef DFJK_X_STAGE
+#undef DFJK_X_CDMA
 #undef DFJK_X_LOAD
+#undef DFJK_CSB
 
   if (rowdot) {
     // row dot = sum over the eight lanes of the row, fixed order
