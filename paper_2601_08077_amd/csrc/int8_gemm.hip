@@ -326,8 +326,11 @@ __global__ __launch_bounds__(512) void k_x_int8(
 
 // ---------------------------------------------------------------------------
 // Slicing of X_b (rows mu over k = (P - P0) * nocc + i, stored contiguously by
-// the X kernel's blocked layout) into Xd[a][b][mu][k], natural k order, zero
-// padded to nao_pad rows and kbp columns.  One thread per 16 consecutive k.
+// the X kernel's blocked layout) into digit planes tiled by 64-wide k steps:
+// plane a, block b, step ks holds nao_pad rows of 64 bytes (k = 64 ks .. +63
+// in natural order), zero padded; element (a, b, mu, k) sits at
+// a plane + ((b nks + k / 64) nao_pad + mu) 64 + k % 64, nks = kbp / 64.  One
+// thread per 16 consecutive k; four neighbouring threads fill one 64-byte row.
 // ---------------------------------------------------------------------------
 template <int S>
 __global__ __launch_bounds__(256) void k_slice_x(const double* __restrict__ Xb, int64_t naux,
@@ -336,16 +339,19 @@ __global__ __launch_bounds__(256) void k_slice_x(const double* __restrict__ Xb, 
                                                  const unsigned long long* __restrict__ xmax,
                                                  int32_t* __restrict__ F,
                                                  int8_t* __restrict__ Xd) {
-  const int nkc = kbp >> 4;
-  const int64_t total = (int64_t)nb * nao_pad * nkc;
+  const int nks = kbp >> 6;
+  const int64_t total = (int64_t)nb * nks * nao_pad * 4;
   const int64_t plane = (int64_t)nb * nao_pad * kbp;
   const int64_t kfull = (int64_t)pblk * nocc;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const int kc = (int)(idx % nkc);
-    const int64_t rest = idx / nkc;
+    const int part = (int)(idx & 3);
+    const int64_t rest = idx >> 2;
     const int mu = (int)(rest % nao_pad);
-    const int b = (int)(rest / nao_pad);
+    const int64_t bks = rest / nao_pad;  // b nks + ks
+    const int ks = (int)(bks % nks);
+    const int b = (int)(bks / nks);
+    const int kc = ks * 4 + part;         // 16-wide k unit within the block
     const int64_t p0 = (int64_t)b * pblk;
     const int64_t p1 = p0 + pblk < naux ? p0 + pblk : naux;
     const int kb = (int)((p1 - p0) * nocc);
@@ -369,7 +375,7 @@ __global__ __launch_bounds__(256) void k_slice_x(const double* __restrict__ Xb, 
         wd[j] = (mu < nao && k < kb) ? digit_word(src[j], e) : 0ull;
       }
     }
-    int8_t* dst = Xd + ((int64_t)b * nao_pad + mu) * kbp + kc * 16;
+    int8_t* dst = Xd + (bks * nao_pad + mu) * 64 + part * 16;
 #pragma unroll
     for (int a = 0; a < S; ++a) {
       uint4 pk;
@@ -392,18 +398,25 @@ __device__ __forceinline__ void lower_tile(int idx, int& t1, int& t2) {
 
 // ---------------------------------------------------------------------------
 // K partials: Kp[grp][mu][nu] = sum over blocks b of group grp (ascending) of
-// recombine(S_g of X_b X_b^T), on lower 64x64 tiles; 4 waves x (32 x 32).
-// Per 64-wide k step the two row panels (S planes x 64 rows x 64 B each; one
-// panel on diagonal tiles) are staged in LDS by the whole workgroup; the next
-// step's panels are prefetched into registers while the current step runs.
+// recombine(S_g of X_b X_b^T), on lower 64x64 tiles; 8 waves x (32 x 16).
+// Per 64-wide k step the two row panels (S planes x 64 rows x 64 B each, the
+// rows of tile row t1 and of tile column t2) are copied straight from the
+// tiled digit planes into one of two LDS stages (buffer loads to LDS, 1 KB =
+// 16 rows per wave instruction), while the MFMAs run on the other stage; one
+// barrier per step.
 // ---------------------------------------------------------------------------
 template <int S>
 __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
                                                 const int32_t* __restrict__ F, int nb, int nao,
                                                 int nao_pad, int kbp, int groups,
                                                 double* __restrict__ Kp) {
-  constexpr int ROW = 64;  // 64 B rows, 16-byte units swizzled (swz)
-  __shared__ __attribute__((aligned(16))) int8_t Ls[2][S][64][ROW];
+  constexpr int ROW = 64;             // 64 B rows, 16-byte units swizzled (swz)
+  constexpr int NCP = 2 * S * 4;      // 1 KB copies per step (2 panels x S planes x 4)
+  constexpr int CPW = (NCP + 7) / 8;  // per wave; waves past the last copy fill spare rows
+  // stages as separate arrays (the compiler can tell the stage being copied
+  // into from the one being read); rows [panel][a][64], then 16 spare rows
+  __shared__ __attribute__((aligned(16))) int8_t L0[2 * S * 64 + 16][ROW];
+  __shared__ __attribute__((aligned(16))) int8_t L1[2 * S * 64 + 16][ROW];
   // group-major logical order, dealt to the XCDs in consecutive ranges: the
   // tiles of one group (which stream the same X_b panels) share an L2
   const int64_t ntile = gridDim.x;
@@ -413,68 +426,68 @@ __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
   lower_tile((int)(lid - grp * ntile), t1, t2);
   const int b_lo = (int)((int64_t)grp * nb / groups);
   const int b_hi = (int)((int64_t)(grp + 1) * nb / groups);
-  // 8 waves, each a 32 x 16 piece of the 64 x 64 tile (two row fragments, one
-  // column fragment): small enough per wave for two waves per SIMD.
   const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
   const int wr = (w >> 2) * 32, wc = (w & 3) * 16;
-  const int64_t plane = (int64_t)nb * nao_pad * kbp;
-  const int ksteps = kbp >> 6;
-  // loader: threads 0..255 move the row panel (tile row t1), 256..511 the column
-  // panel (t2); thread u moves row u/4, 16-byte part u%4 of every plane
-  const int panel = t >> 8, u = t & 255, lrow = u >> 2, lpart = u & 3;
-  const int8_t* src = Xd + (int64_t)((panel ? t2 : t1) * 64 + lrow) * kbp + lpart * 16;
-  const int ldst = panel * S * 64 * ROW + lrow * ROW + swz(lrow, lpart);
-  i32x4 pre[S];
-#define DFJK_K_LOAD_STEP(BB, K0)                                                               \
-  {                                                                                            \
-    const int64_t off_ = (int64_t)(BB) * nao_pad * kbp + (K0);                                 \
-    _Pragma("unroll") for (int a = 0; a < S; ++a)                                              \
-      pre[a] = *reinterpret_cast<const i32x4*>(src + a * plane + off_);                        \
+  const int64_t plane = (int64_t)nb * nao_pad * kbp, bstride = (int64_t)nao_pad * kbp;
+  const int nks = kbp >> 6;
+  // copy j of this wave: panel, plane a, 16-row quarter; lane l lands at byte
+  // 16 l of the block (row quarter*16 + l/4, unit l%4), so it fetches the
+  // 16-byte unit that the row swizzle puts there
+  int cpa[CPW], voff[CPW], crow[CPW];
+  const int wu = __builtin_amdgcn_readfirstlane(w);  // wave-uniform copy of w
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int cid = wu + 8 * j;
+    const int c = cid < NCP ? cid : 0;
+    const int panel = c / (4 * S), a = (c / 4) % S, quarter = c % 4;
+    const int row = quarter * 16 + (l >> 2), part = (l & 3) ^ ((row >> 1) & 3);
+    cpa[j] = a;
+    voff[j] = ((panel ? t2 : t1) * 64 + row) * 64 + part * 16;
+    crow[j] = cid < NCP ? (panel * S + a) * 64 + quarter * 16 : 2 * S * 64;
   }
+  auto copy_step = [&](auto& L, int b, int ks) {
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<int8_t*>(Xd + cpa[j] * plane + b * bstride), (short)0, (int)bstride,
+          0x00020000);
+      copy16_to_lds(r, &L[crow[j]][0], voff[j], ks * nao_pad * 64);
+    }
+  };
 
   double kacc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) kacc[i][r] = 0.0;
+  i32x4 acc[S][2];
+#pragma unroll
+  for (int g = 0; g < S; ++g)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) acc[g][i] = i32x4{0, 0, 0, 0};
 
-  if (b_lo < b_hi) DFJK_K_LOAD_STEP(b_lo, 0)
-  for (int b = b_lo; b < b_hi; ++b) {
-    i32x4 acc[S][2];
+  // MFMAs of one step on stage L
+  auto mma_step = [&](auto& L) {
+    i32x4 bf[S];
 #pragma unroll
-    for (int g = 0; g < S; ++g)
+    for (int bb = 0; bb < S; ++bb)
+      bf[bb] = *reinterpret_cast<const i32x4*>(&L[(S + bb) * 64 + wc + r16][swz(wc + r16, q)]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) acc[g][i] = i32x4{0, 0, 0, 0};
-    for (int ks = 0; ks < ksteps; ++ks) {
-      __syncthreads();
+    for (int i = 0; i < 2; ++i) {
+      i32x4 af[S];
+      const int row = wr + i * 16 + r16;
 #pragma unroll
       for (int a = 0; a < S; ++a)
-        *reinterpret_cast<i32x4*>(&Ls[0][0][0][0] + ldst + a * 64 * ROW) = pre[a];
-      __syncthreads();
-      {
-        const bool last = ks + 1 == ksteps;
-        const int nb_ = last ? b + 1 : b;
-        const int nk_ = last ? 0 : (ks + 1) * 64;
-        if (nb_ < b_hi) DFJK_K_LOAD_STEP(nb_, nk_)
-      }
-      i32x4 bf[S];
+        af[a] = *reinterpret_cast<const i32x4*>(&L[a * 64 + row][swz(row, q)]);
 #pragma unroll
-      for (int bb = 0; bb < S; ++bb)
-        bf[bb] = *reinterpret_cast<const i32x4*>(&Ls[1][bb][wc + r16][swz(wc + r16, q)]);
+      for (int a = 0; a < S; ++a)
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        i32x4 af[S];
-#pragma unroll
-        for (int a = 0; a < S; ++a)
-          af[a] = *reinterpret_cast<const i32x4*>(&Ls[0][a][wr + i * 16 + r16][swz(wr + i * 16 + r16, q)]);
-#pragma unroll
-        for (int a = 0; a < S; ++a)
-#pragma unroll
-          for (int bb = 0; bb < S - a; ++bb)
-            acc[a + bb][i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[bb], acc[a + bb][i], 0, 0, 0);
-      }
+        for (int bb = 0; bb < S - a; ++bb)
+          acc[a + bb][i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[bb], acc[a + bb][i], 0, 0, 0);
     }
-    // end of aux block b: recombine into the FP64 partial sum
+  };
+  // end of aux block b: recombine into the FP64 partial sum
+  auto close_block = [&](int b) {
     const int32_t* Fb = F + (int64_t)b * nao_pad;
     const int fn = Fb[t2 * 64 + wc + r16];
 #pragma unroll
@@ -487,9 +500,40 @@ __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
         for (int g = S + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][i][r], base - 8 * g);
         kacc[i][r] += z;
       }
+#pragma unroll
+    for (int g = 0; g < S; ++g)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[g][i] = i32x4{0, 0, 0, 0};
+  };
+
+  // steps (b, ks) in order; step n uses stage n % 2
+  int b = b_lo, ks = 0;
+  if (b < b_hi) copy_step(L0, b, 0);
+  __syncthreads();
+  while (b < b_hi) {
+    // even step on L0, the next one copied into L1
+    {
+      const int nb_ = ks + 1 == nks ? b + 1 : b, nk_ = ks + 1 == nks ? 0 : ks + 1;
+      if (nb_ < b_hi) copy_step(L1, nb_, nk_);
+      mma_step(L0);
+      if (ks + 1 == nks) close_block(b);
+      __syncthreads();  // L0 may be overwritten; this wave's copies into L1 have landed
+      b = nb_;
+      ks = nk_;
+    }
+    if (b >= b_hi) break;
+    // odd step on L1, the next one copied into L0
+    {
+      const int nb_ = ks + 1 == nks ? b + 1 : b, nk_ = ks + 1 == nks ? 0 : ks + 1;
+      if (nb_ < b_hi) copy_step(L0, nb_, nk_);
+      mma_step(L1);
+      if (ks + 1 == nks) close_block(b);
+      __syncthreads();
+      b = nb_;
+      ks = nk_;
+    }
   }
 
-#undef DFJK_K_LOAD_STEP
   double* out = Kp + (int64_t)grp * nao * nao;
   const int nu = t2 * 64 + wc + r16;
 #pragma unroll
@@ -613,7 +657,7 @@ hipError_t launch_slice_x(hipStream_t st, int s, const double* X, int64_t naux, 
                           int nocc, int pblk, int nao_pad, int kbp,
                           const unsigned long long* xmax, int32_t* F, int8_t* Xd) {
   const int nb = (int)((naux + pblk - 1) / pblk);
-  const int64_t total = (int64_t)nb * nao_pad * (kbp / 16);
+  const int64_t total = (int64_t)nb * nao_pad * (kbp / 16);  // threads (16 k each)
   if (total <= 0) return hipSuccess;
   int64_t g = (total + 255) / 256;
   if (g > 65536) g = 65536;
