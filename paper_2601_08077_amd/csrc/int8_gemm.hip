@@ -110,7 +110,8 @@ __global__ __launch_bounds__(512) void k_x_int8(
     const int per_plane = NT * 4 * KSUB;
     const int a = uu / per_plane, rem = uu - a * per_plane;
     const int col = rem / (4 * KSUB), part = rem - col * (4 * KSUB);
-    csrc[i] = dC + ((int64_t)a * ncp + n0 + col) * kp + part * 16;
+    // C digit planes tiled by 64-wide k chunks: (a, chunk c, column) rows of 64 B
+    csrc[i] = dC + ((int64_t)(a * (kp >> 6) + (part >> 2)) * ncp + n0 + col) * 64 + (part & 3) * 16;
     cdst[i] = (a * NT + col) * ROW + (part >> 2) * 64 + swz(col, part & 3);
   }
 
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
       const int u0 = (ins < CINS ? ins : 0) * 64;
       const int a = u0 / (NT * 4 * KSUB), col0 = (u0 - a * NT * 4 * KSUB) / (4 * KSUB);
       const int col = col0 + (l >> 2), part = (l & 3) ^ ((col >> 1) & 3);
-      coff[j] = (a * ncp + n0 + col) * kp + part * 16;
+      coff[j] = ((a * (kp >> 6)) * ncp + n0 + col) * 64 + part * 16;
     }
   }
 
@@ -172,7 +173,8 @@ __global__ __launch_bounds__(512) void k_x_int8(
     }                                                                                      \
     if constexpr (NBUF == 1) {                                                             \
       _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                   \
-        if (t + 512 * i < CUNITS) cpre[i] = *reinterpret_cast<const i32x4*>(csrc[i] + kb0); \
+        if (t + 512 * i < CUNITS)                                                          \
+          cpre[i] = *reinterpret_cast<const i32x4*>(csrc[i] + (int64_t)(kb0 >> 6) * ncp * 64); \
       }                                                                                    \
     }                                                                                      \
   }
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
     /* block ins: plane a, columns col0 .. col0 + 15 (spare rows past the last) */        \
     const int row0 = ins < CINS ? (ins * 64) / 4 : S * NT;                                 \
     int8_t* dst = &DFJK_CSB(BUF)[row0][0];                                                  \
-    copy16_to_lds(crsrc, dst, coff[j], (CC) * KC);                                         \
+    copy16_to_lds(crsrc, dst, coff[j], (CC) * ncp * 64);                                   \
   }
 
   // Digits of the chunk whose B values and C digits sit in registers, into

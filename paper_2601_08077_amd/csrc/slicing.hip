@@ -62,11 +62,12 @@ __global__ void k_slice_rows(const double* __restrict__ A, int64_t rows, int64_t
   }
 }
 
-// Digit planes of C^T in the right-operand layout of the INT8 X product:
-// dC[a][i][p] with p = 64 c + 16 q + 8 b + 2 j + h holding
+// Digit planes of C^T in the right-operand layout of the INT8 X product,
+// tiled by 64-wide k chunks: plane a, chunk c, column i holds 64 bytes at
+// a ncp kp + (c ncp + i) 64, byte p = 16 q + 8 b + 2 j + h holding
 // k = 64 c + 16 j + 4 q + 2 b + h (the order in which the B-tile loader's
-// eight lanes per row place their values in the four MFMA lane groups), or
-// p = k when `natural` is set (X from B digit planes).
+// eight lanes per row place their values in the four MFMA lane groups).
+// With `natural` set: dC[a][i][k] in natural order (X from B digit planes).
 __global__ void k_slice_c(const double* __restrict__ C, int64_t nao, int64_t nocc, int s,
                           const int32_t* __restrict__ f, int ncp, int kp, int natural,
                           int8_t* __restrict__ dC) {
@@ -77,9 +78,10 @@ __global__ void k_slice_c(const double* __restrict__ C, int64_t nao, int64_t noc
     const int p = (int)(idx - (int64_t)i * kp);
     const int c = p >> 6, q = (p >> 4) & 3, b = (p >> 3) & 1, j = (p >> 1) & 3, h = p & 1;
     const int64_t k = natural ? p : (int64_t)c * 64 + 16 * j + 4 * q + 2 * b + h;
+    const int64_t o = natural ? idx : ((int64_t)c * ncp + i) * 64 + (p & 63);
     uint64_t w = 0;
     if (i < nocc && k < nao) w = digit_word(C[k * nocc + i], f[i]);
-    for (int a = 0; a < s; ++a) dC[(int64_t)a * n + idx] = (int8_t)digit_byte(w, a + 1);
+    for (int a = 0; a < s; ++a) dC[(int64_t)a * n + o] = (int8_t)digit_byte(w, a + 1);
   }
 }
 
