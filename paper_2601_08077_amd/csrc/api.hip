@@ -19,6 +19,7 @@ struct df_ctx {
   int pblk = 64;
   int k_groups_req = 0;
   int k_groups_used = 0;
+  int ncu = 256;  // compute units of the context's device
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int* status = nullptr;  // device word owned by the context
@@ -89,6 +90,26 @@ size_t carve(size_t& cur, size_t bytes) {
   return o;
 }
 
+// Default number of K partial groups: the count that minimises the K kernel's
+// makespan in workgroup rounds, ceil(tiles g / slots) rounds of ceil(nb / g)
+// aux blocks each (slots = workgroups resident on the device at once), the
+// smallest such g.
+static int default_k_groups(const df_ctx* c, int tiles, int nb) {
+  const int s = c->slices > 0 ? c->slices : 1;
+  const int64_t slots = (int64_t)c->ncu * k_int8_resident(s);
+  int best = 1;
+  int64_t best_cost = -1;
+  for (int g = 1; g <= std::min(nb, 64); ++g) {
+    const int64_t rounds = ((int64_t)tiles * g + slots - 1) / slots;
+    const int64_t cost = rounds * ((nb + g - 1) / g);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = g;
+    }
+  }
+  return best;
+}
+
 Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
   Plan p{};
   p.naux = naux;
@@ -105,9 +126,7 @@ Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
   int g = c->k_groups_req;
   if (g <= 0) {
     const auto it = c->tuned.find(std::make_tuple(naux, nao, nocc, c->slices, c->pblk));
-    g = it != c->tuned.end()
-            ? it->second.first
-            : (int)std::min<int64_t>(std::max<int64_t>(1, (1024 + tiles - 1) / tiles), 64);
+    g = it != c->tuned.end() ? it->second.first : default_k_groups(c, tiles, p.nb);
   }
   p.groups = std::max(1, std::min(g, p.nb));
   if (!c->blk_s.empty()) p.groups = p.nb;  // per-block precision: one partial per block
@@ -391,6 +410,13 @@ int df_create(df_ctx** ctx, void* hip_stream) {
   *ctx = nullptr;
   df_ctx* c = new df_ctx();
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      c->ncu = n;
+    clear_stale_error();
+  }
   hipError_t e = hipMalloc(&c->status, 256);
   if (e != hipSuccess) {
     fprintf(stderr, "df_create: hipMalloc: %s\n", hipGetErrorString(e));

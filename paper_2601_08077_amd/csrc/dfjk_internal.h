@@ -157,6 +157,8 @@ hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, i
 hipError_t launch_slice_x(hipStream_t st, int s, const double* Xb, int64_t naux, int nao,
                           int nocc, int pblk, int nao_pad, int kbp,
                           const unsigned long long* xmax, int32_t* F, int8_t* Xd);
+// Workgroups of the INT8 K kernel for s slices that one CU holds at once.
+int k_int8_resident(int s);
 hipError_t launch_k_int8(hipStream_t st, int s, const int8_t* Xd, const int32_t* F, int nb,
                          int nao, int nao_pad, int kbp, int groups, double* Kp);
 hipError_t launch_debug_pairs(hipStream_t st, int s, const int8_t* a_dig, const int8_t* b_dig,

@@ -681,6 +681,31 @@ hipError_t launch_slice_x(hipStream_t st, int s, const double* X, int64_t naux, 
   return hipGetLastError();
 }
 
+int k_int8_resident(int s) {
+  static int cached[9] = {0};  // per slice count (the same on every MI355X)
+  if (s < 1 || s > 8) return 1;
+  if (cached[s] > 0) return cached[s];
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define DFJK_KOCC(SS) \
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_k_int8<SS>), 512, 0)
+  switch (s) {
+    case 1: DFJK_KOCC(1); break;
+    case 2: DFJK_KOCC(2); break;
+    case 3: DFJK_KOCC(3); break;
+    case 4: DFJK_KOCC(4); break;
+    case 5: DFJK_KOCC(5); break;
+    case 6: DFJK_KOCC(6); break;
+    case 7: DFJK_KOCC(7); break;
+    case 8: DFJK_KOCC(8); break;
+    default: break;
+  }
+#undef DFJK_KOCC
+  if (e != hipSuccess) (void)hipGetLastError();  // leave no error for the next launch check
+  cached[s] = e == hipSuccess && n > 0 ? n : 1;
+  return cached[s];
+}
+
 hipError_t launch_k_int8(hipStream_t st, int s, const int8_t* Xd, const int32_t* F, int nb,
                          int nao, int nao_pad, int kbp, int groups, double* Kp) {
   const int nt = nao_pad / 64;
