@@ -125,6 +125,15 @@ __global__ __launch_bounds__(512) void k_x_int8(
   const __amdgpu_buffer_rsrc_t crsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<int8_t*>(dC), (short)0, S * ncp * kp, 0x00020000);
   int coff[NBUF == 2 ? CIW : 1];
+  // Two-stage full-K path: B and D rows are read by buffer loads too (byte
+  // offsets from resources over this tile's 64 rows of B and of D, chunk
+  // offset in a scalar), so no address registers are rewritten per chunk.
+  const __amdgpu_buffer_rsrc_t brsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(B + m0 * (int64_t)K), (short)0, 64 * K * 8, 0x00020000);
+  const __amdgpu_buffer_rsrc_t drsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>((want_rd ? D : B) + (m0 % nao) * (int64_t)K), (short)0, 64 * K * 8,
+      0x00020000);
+  const int vbo = (lrow * K + 2 * lm) * 8;
   if constexpr (NBUF == 2) {
 #pragma unroll
     for (int j = 0; j < CIW; ++j) {
@@ -148,7 +157,18 @@ __global__ __launch_bounds__(512) void k_x_int8(
 #define DFJK_X_LOAD(CC)                                                                    \
   {                                                                                        \
     const int kb0 = (CC) * KC;                                                             \
-    if (FULLK) {                                                                           \
+    if constexpr (NBUF == 2 && FULLK) {                                                    \
+      _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                      \
+        const double2 pb = __builtin_bit_cast(                                             \
+            double2, __builtin_amdgcn_raw_buffer_load_b128(brsrc, vbo + 128 * j, kb0 * 8, 0)); \
+        const double2 pd = __builtin_bit_cast(                                             \
+            double2, __builtin_amdgcn_raw_buffer_load_b128(drsrc, vbo + 128 * j, kb0 * 8, 0)); \
+        v[2 * j] = pb.x;                                                                   \
+        v[2 * j + 1] = pb.y;                                                               \
+        dv[2 * j] = pd.x;                                                                  \
+        dv[2 * j + 1] = pd.y;                                                              \
+      }                                                                                    \
+    } else if (FULLK) {                                                                    \
       _Pragma("unroll") for (int j = 0; j < NV / 2; ++j) {                                 \
         const int off = kb0 + 64 * (j >> 2) + 16 * (j & 3);                                \
         const double2 p = *reinterpret_cast<const double2*>(brow + off);                   \
@@ -244,21 +264,28 @@ __global__ __launch_bounds__(512) void k_x_int8(
     __builtin_amdgcn_s_waitcnt(0);  // this wave's C digits have landed in LDS
     __syncthreads();
     // One step with chunk c in stage BB: stage chunk cn's A digits into the
-    // other stage, issue the loads of chunk cnn, start the copy of chunk cn's
-    // C digits into the other stage (after the loads: the compiler waits for
-    // every pending copy before it reuses a register), multiply chunk c and
-    // meet at the barrier (which waits for this wave's copies and loads).
+    // other stage, start the copy of chunk cn's C digits into the other stage,
+    // issue the loads of chunk cnn (after the copies, in this order), multiply
+    // chunk c and meet at the barrier.  Full K: the barrier is written out
+    // (s_waitcnt + s_barrier, a compiler memory barrier) and waits only for
+    // this wave's copies and LDS stores: the loads of chunk cnn, exactly 8
+    // vector-memory operations issued after the copies, stay in flight into
+    // the next step.  Ragged K: a workgroup barrier (waits for everything).
+    static_assert(NV == 8, "two-stage X loop assumes 8 values per lane and chunk");
 #define DFJK_X_STEP(BB)                                                                         \
   {                                                                                             \
     const int cnn = next_of(cn);                                                                \
     if (cn >= 0) DFJK_X_STAGE(1 - (BB))                                                         \
     __builtin_amdgcn_sched_barrier(0);                                                          \
-    if (cnn >= 0) DFJK_X_LOAD(cnn)                                                              \
-    __builtin_amdgcn_sched_barrier(0);                                                          \
     if (cn >= 0) DFJK_X_CDMA(1 - (BB), cn)                                                      \
     __builtin_amdgcn_sched_barrier(0);                                                          \
+    if (cnn >= 0) DFJK_X_LOAD(cnn)                                                              \
+    __builtin_amdgcn_sched_barrier(0);                                                          \
     DFJK_X_MMA(BB)                                                                              \
-    __syncthreads();                                                                            \
+    if (FULLK && cnn >= 0)                                                                      \
+      asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");                 \
+    else                                                                                        \
+      __syncthreads();                                                                          \
     c = cn;                                                                                     \
     cn = cnn;                                                                                   \
   }
