@@ -92,11 +92,11 @@ size_t carve(size_t& cur, size_t bytes) {
 
 // Default number of K partial groups: the count that minimises the K kernel's
 // makespan in workgroup rounds, ceil(tiles g / slots) rounds of ceil(nb / g)
-// aux blocks each (slots = workgroups resident on the device at once), the
-// smallest such g.
+// aux blocks each (slots = workgroups resident on the device at once, taken
+// at the largest slice count so that g, and with it the workspace size, does
+// not depend on the slice count), the smallest such g.
 static int default_k_groups(const df_ctx* c, int tiles, int nb) {
-  const int s = c->slices > 0 ? c->slices : 1;
-  const int64_t slots = (int64_t)c->ncu * k_int8_resident(s);
+  const int64_t slots = (int64_t)c->ncu * k_int8_resident(kMaxSlices);
   int best = 1;
   int64_t best_cost = -1;
   for (int g = 1; g <= std::min(nb, 64); ++g) {

@@ -225,6 +225,18 @@ def test_groups_change_only_the_summation_order(torch_dev, ctx):
         assert np.array_equal(got["K"], ref["K"])
 
 
+def test_workspace_size_does_not_depend_on_slices(torch_dev, ctx):
+    """One workspace sized at any precision serves builds at every precision
+    (the default K group count must not change with s)."""
+    ctx.df_set_k_groups(0)
+    ctx.df_set_pblk(64)
+    sizes = set()
+    for s in range(0, 9):
+        ctx.df_set_precision(s)
+        sizes.add(ctx.df_workspace_size(3072, 768, 96))
+    assert len(sizes) == 1
+
+
 def test_run_twice_is_bitwise_reproducible(torch_dev, ctx):
     torch = torch_dev
     p = _problem(130, 65, 100, True)
