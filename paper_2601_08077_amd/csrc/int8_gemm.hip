@@ -643,14 +643,15 @@ hipError_t launch_x_sk(hipStream_t st, const double* B, int64_t M, int nao, cons
   return hipGetLastError();
 }
 
-// Chunks of 128 k (two MFMA k steps, twice the bytes in flight per load) where
-// the registers allow it (s <= 5) and nao is a multiple of 128.
+// Chunks of 128 k (two MFMA k steps, one LDS stage) only when asked for
+// (ksub = 2, an autotuner choice; s <= 5 and nao a multiple of 128); by default
+// 64-wide chunks in two LDS stages with direct C copies and buffer loads.
 template <int S>
 hipError_t launch_x_s(hipStream_t st, const double* B, int64_t M, int nao, const int32_t* b_exp,
                       const int8_t* dC, int ncp, int kp, const int32_t* f_col, int nocc,
                       double* X, int xlayout, unsigned long long* xmax, int pblk, const double* D,
                       double* rowdot, const unsigned long long* cmask, int ksub) {
-  if (S <= 5 && nao % 128 == 0 && ksub != 1)
+  if (S <= 5 && nao % 128 == 0 && ksub == 2)
     return launch_x_sk<S, true, (S <= 5 ? 2 : 1)>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X,
                                                    xlayout, xmax, pblk, D, rowdot, cmask);
   if (nao % 64 == 0)
