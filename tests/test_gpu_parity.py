@@ -171,9 +171,28 @@ def _check_coulomb(got, fp, p):
 @pytest.mark.parametrize("s", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda t: "x".join(map(str, t[:4])))
 def test_emulated_build_bit_exact(torch_dev, ctx, s, shape):
-    torch = torch_dev
     nao, naux, nocc, pblk, rs = shape
-    p = _problem(nao, naux, nocc, rs)
+    _check_emulated(torch_dev, ctx, _problem(nao, naux, nocc, rs), s, pblk)
+
+
+@pytest.mark.parametrize("s", [3, 7])
+def test_zero_rows_columns_and_slices_bit_exact(torch_dev, ctx, s):
+    """Degenerate operands: basis function 3 absent from every B_P (zero row and
+    column, exponent 0 by the slicing rule), aux slice 17 identically zero, and a
+    zero orbital column of C (so D = occ C C^T has a zero direction)."""
+    p = dict(_problem(70, 100, 33, True, seed=5))
+    B = p["B"].copy()
+    B[:, 3, :] = 0.0
+    B[:, :, 3] = 0.0
+    B[17] = 0.0
+    C = p["C"].copy()
+    C[:, 5] = 0.0
+    p.update(B=B, C=C, D=p["occ"] * (C @ C.T))
+    _check_emulated(torch_dev, ctx, p, s, 64)
+
+
+def _check_emulated(torch, ctx, p, s, pblk):
+    naux, nao, _ = p["B"].shape
     got = _run_build(torch, ctx, p, s, pblk)
     ref = em.emulated_build_jk(p["B"], p["C"], s, occ=p["occ"], D=p["D"], pblk=pblk,
                                groups=got["groups"])

@@ -97,9 +97,28 @@ def test_prepare_b_bit_exact(torch_dev, ctx, planes, nao, naux):
 @pytest.mark.parametrize("s", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda t: "x".join(map(str, t[:4])))
 def test_sliced_build_bit_exact(torch_dev, ctx, s, shape):
-    torch = torch_dev
     nao, naux, nocc, pblk, rs = shape
-    p = _problem(nao, naux, nocc, rs)
+    _check_sliced(torch_dev, ctx, _problem(nao, naux, nocc, rs), s, pblk)
+
+
+@pytest.mark.parametrize("s", [3, 7])
+def test_sliced_zero_rows_columns_and_slices_bit_exact(torch_dev, ctx, s):
+    """Zero rows of B and of D (exponent 0), a zero aux slice (rho_P = 0, so
+    w_P = 0 in the digit J) and a zero orbital column of C."""
+    p = dict(_problem(70, 100, 33, True, seed=5))
+    B = p["B"].copy()
+    B[:, 3, :] = 0.0
+    B[:, :, 3] = 0.0
+    B[17] = 0.0
+    C = p["C"].copy()
+    C[:, 5] = 0.0
+    C[3, :] = 0.0
+    p.update(B=B, C=C, D=p["occ"] * (C @ C.T))
+    _check_sliced(torch_dev, ctx, p, s, 64)
+
+
+def _check_sliced(torch, ctx, p, s, pblk):
+    naux, nao, _ = p["B"].shape
     got = _run_sliced(torch, ctx, p, s, 8, pblk)
     ref = em.sliced_build_jk(p["B"], p["C"], s, occ=p["occ"], D=p["D"], pblk=pblk,
                              groups=got["groups"])
