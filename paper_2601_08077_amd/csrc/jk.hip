@@ -230,26 +230,40 @@ __global__ __launch_bounds__(256) void k_bound(const double* __restrict__ scratc
                                                double kappa2_full, double kappa2_last, double occ,
                                                int occ_pow2, const int32_t* __restrict__ sblk,
                                                double* __restrict__ err_bound) {
+  // lane: one nu of the 256-wide column chunk blockIdx.x; the workgroup's
+  // KB_ROWS rows mu (blockIdx.y) are the same for every lane, so each lane reads
+  // its nu terms once per block and the mu terms are uniform loads
+  constexpr int KB_ROWS = 8;
   const double u = 0x1p-53;
   const double accf = (nb - 1) * u * pow(1.0 + u, (double)nb);
-  double best = 0.0;
-  const int64_t nn = (int64_t)nao * nao;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int mu = (int)(e / nao), nu = (int)(e - (int64_t)mu * nao);
-    double sum = 0.0, kabs = 0.0;
-    for (int b = 0; b < nb; ++b) {
+  const int nu = blockIdx.x * 256 + threadIdx.x;
+  const int mu0 = blockIdx.y * KB_ROWS;
+  const bool live = nu < nao;
+  const int nuc = live ? nu : 0;
+  double sum[KB_ROWS], kabs[KB_ROWS];
+#pragma unroll
+  for (int m = 0; m < KB_ROWS; ++m) sum[m] = kabs[m] = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const double* sn = scratch + 3 * ((int64_t)b * nao + nuc);
+    const double sn0 = sn[0], sn2 = sn[2];
+    const int64_t p0 = (int64_t)b * pblk;
+    const int64_t kb = ((p0 + pblk < naux ? p0 + pblk : naux) - p0) * nocc;
+    const double k2 = sblk ? kappa_of(sblk[b], kb) : (b == nb - 1 ? kappa2_last : kappa2_full);
+#pragma unroll
+    for (int m = 0; m < KB_ROWS; ++m) {
+      const int mu = mu0 + m < nao ? mu0 + m : nao - 1;
       const double* sm = scratch + 3 * ((int64_t)b * nao + mu);
-      const double* sn = scratch + 3 * ((int64_t)b * nao + nu);
-      const int64_t p0 = (int64_t)b * pblk;
-      const int64_t kb = ((p0 + pblk < naux ? p0 + pblk : naux) - p0) * nocc;
-      const double pp = sm[2] * sn[2];
-      const double k2 = sblk ? kappa_of(sblk[b], kb) : (b == nb - 1 ? kappa2_last : kappa2_full);
-      sum += sm[0] * sn[2] + (sm[2] + sm[1]) * sn[0] + (double)kb * pp * k2;
-      kabs += (double)kb * pp * (1.0 + k2);
+      const double pp = sm[2] * sn2;
+      sum[m] += sm[0] * sn2 + (sm[2] + sm[1]) * sn0 + (double)kb * pp * k2;
+      kabs[m] += (double)kb * pp * (1.0 + k2);
     }
-    double bound = fabs(occ) * (sum + accf * kabs);
-    if (!occ_pow2) bound += u * fabs(occ) * kabs;
+  }
+  double best = 0.0;
+#pragma unroll
+  for (int m = 0; m < KB_ROWS; ++m) {
+    if (!live || mu0 + m >= nao) continue;
+    double bound = fabs(occ) * (sum[m] + accf * kabs[m]);
+    if (!occ_pow2) bound += u * fabs(occ) * kabs[m];
     best = fmax(best, bound);
   }
 #pragma unroll
@@ -327,10 +341,9 @@ hipError_t launch_bound(hipStream_t st, const int32_t* b_exp, const int32_t* f_c
     const double m = frexp(occ, &ex);
     occ_pow2 = (m == 0.5 || m == -0.5) ? 1 : 0;
   }
-  const int64_t nn = (int64_t)nao * nao;
-  int64_t g2 = (nn + 255) / 256;
-  if (g2 > 2048) g2 = 2048;
-  hipLaunchKernelGGL(k_bound, dim3((unsigned)g2), dim3(256), 0, st, scratch, nao, nb, naux, pblk,
+  // 256 columns nu by 8 rows mu per workgroup (the row count is k_bound's)
+  const dim3 g2((unsigned)((nao + 255) / 256), (unsigned)((nao + 7) / 8));
+  hipLaunchKernelGGL(k_bound, g2, dim3(256), 0, st, scratch, nao, nb, naux, pblk,
                      nocc, kappa2_full, kappa2_last, occ, occ_pow2, sblk, err_bound);
   return hipGetLastError();
 }
