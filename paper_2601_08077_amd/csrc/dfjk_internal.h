@@ -30,14 +30,18 @@ __device__ __forceinline__ int exp_of_max(double m) {
 // the two's-complement bytes of N into the balanced digits in [-128, 127]
 // (each low byte u becomes u - 128 once the carries of the +0x80 have moved
 // up).  Requires |a| < 2^e (e is the exponent of the row maximum).
-__device__ __forceinline__ uint64_t digit_word(double a, int e) {
+// digit_word_offset stops before the flip (its seven low bytes still carry the
+// 0x80 offset), for callers that flip whole packed words later.
+__device__ __forceinline__ uint64_t digit_word_offset(double a, int e) {
   const double y = trunc(ldexp(a, 62 - e));
   const double yh = floor(y * 0x1p-32);
   const double yl = fma(-yh, 0x1p32, y);
   const unsigned long long n =
       ((unsigned long long)(unsigned int)(int)yh << 32) | (unsigned long long)(unsigned int)yl;
-  const unsigned long long bias = 0x0080808080808080ull;
-  return (n + bias) ^ bias;
+  return n + 0x0080808080808080ull;
+}
+__device__ __forceinline__ uint64_t digit_word(double a, int e) {
+  return digit_word_offset(a, e) ^ 0x0080808080808080ull;
 }
 
 // Digit k (1-based, 1 = most significant) of a digit word, as a byte.

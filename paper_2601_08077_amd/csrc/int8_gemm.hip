@@ -34,6 +34,48 @@ __device__ __forceinline__ uint32_t pack4(uint64_t w0, uint64_t w1, uint64_t w2,
          (digit_byte(w3, k) << 24);
 }
 
+// 4 x 4 byte transpose of d[0..3] with byte permutes: t[b] holds byte b of
+// d[0], d[1], d[2], d[3] in its bytes 0..3.  (v_perm_b32: selector values 0-3
+// take bytes of the second operand, 4-7 bytes of the first.)
+__device__ __forceinline__ void transpose4x4(const uint32_t d[4], uint32_t t[4]) {
+  const uint32_t p01 = __builtin_amdgcn_perm(d[1], d[0], 0x05010400u);  // d0b0 d1b0 d0b1 d1b1
+  const uint32_t q01 = __builtin_amdgcn_perm(d[1], d[0], 0x07030602u);  // d0b2 d1b2 d0b3 d1b3
+  const uint32_t p23 = __builtin_amdgcn_perm(d[3], d[2], 0x05010400u);
+  const uint32_t q23 = __builtin_amdgcn_perm(d[3], d[2], 0x07030602u);
+  t[0] = __builtin_amdgcn_perm(p23, p01, 0x05040100u);
+  t[1] = __builtin_amdgcn_perm(p23, p01, 0x07060302u);
+  t[2] = __builtin_amdgcn_perm(q23, q01, 0x05040100u);
+  t[3] = __builtin_amdgcn_perm(q23, q01, 0x07060302u);
+}
+
+// Digits 1..S of eight values (one exponent e) as S rows of 8 bytes: row a
+// (0-based) holds digit a + 1 of v[0..7] in its bytes 0..7, the layout that
+// pack4(wd[0..3], a + 1), pack4(wd[4..7], a + 1) gives, formed by byte
+// transposes of the offset words and one flip of the offset per packed word.
+template <int S>
+__device__ __forceinline__ void digit_rows8(const double* v, int e, uint2* out) {
+  uint32_t tr[2][2][4];  // [half of the 8 values][low / high 32 bits][byte]
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    uint32_t lo[4], hi[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint64_t w = digit_word_offset(v[4 * g + j], e);
+      lo[j] = (uint32_t)w;
+      hi[j] = (uint32_t)(w >> 32);
+    }
+    transpose4x4(lo, tr[g][0]);
+    transpose4x4(hi, tr[g][1]);
+  }
+  // digit k (1 = most significant) is byte 8 - k of the word
+#pragma unroll
+  for (int a = 0; a < S; ++a) {
+    const int byte = 7 - a;
+    const uint32_t flip = a == 0 ? 0u : 0x80808080u;
+    out[a] = make_uint2(tr[0][byte >> 2][byte & 3] ^ flip, tr[1][byte >> 2][byte & 3] ^ flip);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // X = B C.  Workgroup: 8 waves, tile 64 rows (P, mu) x 16*NF columns i.  For
 // the MFMAs, waves w and w + 4 own rows 16 (w % 4) .. + 15 and split the
@@ -215,12 +257,10 @@ __global__ __launch_bounds__(512) void k_x_int8(
     /* row-dot terms (zeroed after the loop when there is no D) */                              \
     _Pragma("unroll") for (int j = 0; j < NV; ++j) rd = fma(v[j], dv[j], rd);                   \
     _Pragma("unroll") for (int sub = 0; sub < KSUB; ++sub) {                                    \
-      uint64_t wd[8];                                                                           \
-      _Pragma("unroll") for (int j = 0; j < 8; ++j) wd[j] = digit_word(v[8 * sub + j], e_a);    \
+      uint2 rows[S];                                                                            \
+      digit_rows8<S>(&v[8 * sub], e_a, rows);                                                   \
       _Pragma("unroll") for (int a = 0; a < S; ++a)                                             \
-        *reinterpret_cast<uint2*>(adst + ((BUF) * S + a) * 64 * ROW + sub * 64) =               \
-            make_uint2(pack4(wd[0], wd[1], wd[2], wd[3], a + 1),                                \
-                       pack4(wd[4], wd[5], wd[6], wd[7], a + 1));                               \
+        *reinterpret_cast<uint2*>(adst + ((BUF) * S + a) * 64 * ROW + sub * 64) = rows[a];      \
     }                                                                                           \
     if constexpr (NBUF == 1) {                                                                  \
       _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                        \
