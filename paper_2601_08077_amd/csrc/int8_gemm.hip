@@ -28,12 +28,6 @@ __device__ __forceinline__ void copy16_to_lds(__amdgpu_buffer_rsrc_t r, void* ld
                                            voff, soff, 0, 0);
 }
 
-__device__ __forceinline__ uint32_t pack4(uint64_t w0, uint64_t w1, uint64_t w2, uint64_t w3,
-                                          int k) {
-  return digit_byte(w0, k) | (digit_byte(w1, k) << 8) | (digit_byte(w2, k) << 16) |
-         (digit_byte(w3, k) << 24);
-}
-
 // 4 x 4 byte transpose of d[0..3] with byte permutes: t[b] holds byte b of
 // d[0], d[1], d[2], d[3] in its bytes 0..3.  (v_perm_b32: selector values 0-3
 // take bytes of the second operand, 4-7 bytes of the first.)
@@ -49,9 +43,9 @@ __device__ __forceinline__ void transpose4x4(const uint32_t d[4], uint32_t t[4])
 }
 
 // Digits 1..S of eight values (one exponent e) as S rows of 8 bytes: row a
-// (0-based) holds digit a + 1 of v[0..7] in its bytes 0..7, the layout that
-// pack4(wd[0..3], a + 1), pack4(wd[4..7], a + 1) gives, formed by byte
-// transposes of the offset words and one flip of the offset per packed word.
+// (0-based) holds digit a + 1 of v[j] in its byte j, i.e. byte 7 - a of the
+// digit word of v[j], formed by byte transposes of the offset words and one
+// flip of the offset per packed word (digit 1 carries no offset).
 template <int S>
 __device__ __forceinline__ void digit_rows8(const double* v, int e, uint2* out) {
   uint32_t tr[2][2][4];  // [half of the 8 values][low / high 32 bits][byte]
@@ -429,31 +423,29 @@ __global__ __launch_bounds__(256) void k_slice_x(const double* __restrict__ Xb, 
     if (kc == 0) F[(int64_t)b * nao_pad + mu] = e;
     const double* src = Xb + ((int64_t)b * nao + (mu < nao ? mu : 0)) * kfull + kc * 16;
     const bool full = mu < nao && kc * 16 + 16 <= kb;
-    uint64_t wd[16];
+    // values past the block's k range (and rows past nao) are 0: zero digits
+    double v[16];
     if (full) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const double2 p = *reinterpret_cast<const double2*>(src + 2 * j);
-        wd[2 * j] = digit_word(p.x, e);
-        wd[2 * j + 1] = digit_word(p.y, e);
+        v[2 * j] = p.x;
+        v[2 * j + 1] = p.y;
       }
     } else {
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int k = kc * 16 + j;
-        wd[j] = (mu < nao && k < kb) ? digit_word(src[j], e) : 0ull;
+        v[j] = (mu < nao && k < kb) ? src[j] : 0.0;
       }
     }
+    uint2 r0[S], r1[S];
+    digit_rows8<S>(v, e, r0);
+    digit_rows8<S>(v + 8, e, r1);
     int8_t* dst = Xd + (bks * nao_pad + mu) * 64 + part * 16;
 #pragma unroll
-    for (int a = 0; a < S; ++a) {
-      uint4 pk;
-      pk.x = pack4(wd[0], wd[1], wd[2], wd[3], a + 1);
-      pk.y = pack4(wd[4], wd[5], wd[6], wd[7], a + 1);
-      pk.z = pack4(wd[8], wd[9], wd[10], wd[11], a + 1);
-      pk.w = pack4(wd[12], wd[13], wd[14], wd[15], a + 1);
-      *reinterpret_cast<uint4*>(dst + (int64_t)a * plane) = pk;
-    }
+    for (int a = 0; a < S; ++a)
+      *reinterpret_cast<uint4*>(dst + (int64_t)a * plane) = make_uint4(r0[a].x, r0[a].y, r1[a].x, r1[a].y);
   }
 }
 
