@@ -187,22 +187,33 @@ __global__ __launch_bounds__(512) void k_x_int8(
 #pragma unroll
     for (int f = 0; f < NFW; ++f) acc[g][f] = i32x4{0, 0, 0, 0};
   double rd = 0.0;
+  // Two-stage full-K path: B_P and D are symmetric, so the row dots of rho
+  // need only the chunks up to the tile's diagonal block cdiag (its rows are
+  // mu = 64 cdiag + lrow): chunks below it count twice, the diagonal block by
+  // element (2 below the diagonal, 1 on it, 0 above; exact weights), chunks
+  // past it not at all, and their D rows are not read.
+  constexpr bool TRI = NBUF == 2 && FULLK;
+  const int cdiag = TRI ? (int)((m0 % nao) >> 6) : 0;
 
   double v[NV], dv[NV];
   i32x4 cpre[NBUF == 1 ? CPER : 1];
 #define DFJK_X_LOAD(CC)                                                                    \
   {                                                                                        \
     const int kb0 = (CC) * KC;                                                             \
-    if constexpr (NBUF == 2 && FULLK) {                                                    \
+    if constexpr (TRI) {                                                                   \
       _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                      \
         const double2 pb = __builtin_bit_cast(                                             \
             double2, __builtin_amdgcn_raw_buffer_load_b128(brsrc, vbo + 128 * j, kb0 * 8, 0)); \
-        const double2 pd = __builtin_bit_cast(                                             \
-            double2, __builtin_amdgcn_raw_buffer_load_b128(drsrc, vbo + 128 * j, kb0 * 8, 0)); \
         v[2 * j] = pb.x;                                                                   \
         v[2 * j + 1] = pb.y;                                                               \
-        dv[2 * j] = pd.x;                                                                  \
-        dv[2 * j + 1] = pd.y;                                                              \
+      }                                                                                    \
+      if (want_rd && (CC) <= cdiag) {                                                      \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                    \
+          const double2 pd = __builtin_bit_cast(                                           \
+              double2, __builtin_amdgcn_raw_buffer_load_b128(drsrc, vbo + 128 * j, kb0 * 8, 0)); \
+          dv[2 * j] = pd.x;                                                                \
+          dv[2 * j + 1] = pd.y;                                                            \
+        }                                                                                  \
       }                                                                                    \
     } else if (FULLK) {                                                                    \
       _Pragma("unroll") for (int j = 0; j < NV / 2; ++j) {                                 \
@@ -244,12 +255,22 @@ __global__ __launch_bounds__(512) void k_x_int8(
     copy16_to_lds(crsrc, dst, coff[j], (CC) * ncp * 64);                                   \
   }
 
-  // Digits of the chunk whose B values and C digits sit in registers, into
-  // LDS stage BUF (and its B.D row-dot terms into rd).
-#define DFJK_X_STAGE(BUF)                                                                       \
+  // Digits of chunk CC, whose B values and C digits sit in registers, into
+  // LDS stage BUF (and its B.D row-dot terms into rd / rd_off).
+#define DFJK_X_STAGE(BUF, CC)                                                                   \
   {                                                                                             \
     /* row-dot terms (zeroed after the loop when there is no D) */                              \
-    _Pragma("unroll") for (int j = 0; j < NV; ++j) rd = fma(v[j], dv[j], rd);                   \
+    if constexpr (TRI) {                                                                        \
+      if ((CC) <= cdiag) {                                                                      \
+        _Pragma("unroll") for (int j = 0; j < NV; ++j) {                                        \
+          const int kr = 16 * (j >> 1) + 2 * lm + (j & 1) + 64 * ((CC) - cdiag); /* k - mu0 */  \
+          const double wgt = kr < lrow ? 2.0 : (kr == lrow ? 1.0 : 0.0);                        \
+          rd = fma(v[j] * wgt, dv[j], rd);                                                      \
+        }                                                                                       \
+      }                                                                                         \
+    } else {                                                                                    \
+      _Pragma("unroll") for (int j = 0; j < NV; ++j) rd = fma(v[j], dv[j], rd);                 \
+    }                                                                                           \
     _Pragma("unroll") for (int sub = 0; sub < KSUB; ++sub) {                                    \
       uint2 rows[S];                                                                            \
       digit_rows8<S>(&v[8 * sub], e_a, rows);                                                   \
@@ -292,7 +313,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
     if (c >= 0) {
       DFJK_X_CDMA(0, c)
       DFJK_X_LOAD(c)
-      DFJK_X_STAGE(0)
+      DFJK_X_STAGE(0, c)
     }
     if (cn >= 0) DFJK_X_LOAD(cn)
     __builtin_amdgcn_s_waitcnt(0);  // this wave's C digits have landed in LDS
@@ -309,15 +330,17 @@ __global__ __launch_bounds__(512) void k_x_int8(
 #define DFJK_X_STEP(BB)                                                                         \
   {                                                                                             \
     const int cnn = next_of(cn);                                                                \
-    if (cn >= 0) DFJK_X_STAGE(1 - (BB))                                                         \
+    if (cn >= 0) DFJK_X_STAGE(1 - (BB), cn)                                                     \
     __builtin_amdgcn_sched_barrier(0);                                                          \
     if (cn >= 0) DFJK_X_CDMA(1 - (BB), cn)                                                      \
     __builtin_amdgcn_sched_barrier(0);                                                          \
     if (cnn >= 0) DFJK_X_LOAD(cnn)                                                              \
     __builtin_amdgcn_sched_barrier(0);                                                          \
     DFJK_X_MMA(BB)                                                                              \
-    if (FULLK && cnn >= 0)                                                                      \
+    if (FULLK && cnn >= 0 && want_rd && cnn <= cdiag)                                           \
       asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");                 \
+    else if (FULLK && cnn >= 0)                                                                 \
+      asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");                 \
     else                                                                                        \
       __syncthreads();                                                                          \
     c = cn;                                                                                     \
@@ -334,7 +357,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
     while (c >= 0) {
       const int cn = next_of(c);
       __syncthreads();  // the previous chunk's LDS reads are done
-      DFJK_X_STAGE(0)
+      DFJK_X_STAGE(0, c)
       __syncthreads();  // A and C digits of chunk c are in LDS
       if (cn >= 0) DFJK_X_LOAD(cn)
       DFJK_X_MMA(0)
