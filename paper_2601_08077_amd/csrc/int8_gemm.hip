@@ -261,7 +261,11 @@ __global__ __launch_bounds__(512) void k_x_int8(
   {                                                                                             \
     /* row-dot terms (zeroed after the loop when there is no D) */                              \
     if constexpr (TRI) {                                                                        \
-      if ((CC) <= cdiag) {                                                                      \
+      /* below the diagonal block a uniform doubling (v + v == 2 v exactly); at */              \
+      /* s <= 3 the single weighted form, which keeps two workgroups per CU */                  \
+      if (S >= 4 && (CC) < cdiag) {                                                             \
+        _Pragma("unroll") for (int j = 0; j < NV; ++j) rd = fma(v[j] + v[j], dv[j], rd);        \
+      } else if (S >= 4 ? (CC) == cdiag : (CC) <= cdiag) {                                      \
         _Pragma("unroll") for (int j = 0; j < NV; ++j) {                                        \
           const int kr = 16 * (j >> 1) + 2 * lm + (j & 1) + 64 * ((CC) - cdiag); /* k - mu0 */  \
           const double wgt = kr < lrow ? 2.0 : (kr == lrow ? 1.0 : 0.0);                        \
