@@ -164,7 +164,7 @@ def adaptive_workload(args):
     ctx.df_density(orbs[0], 2.0, D)
     times, below = adaptive.calibrate(ctx, B, be, orbs[0], 2.0, D, J, K, en, eb)
     log(f"calibration ms {times}; FP64 from level {below} down")
-    recs = adaptive.run_sequence(ctx, B, be, orbs, fp64_below_level=below, judge=True)
+    recs = adaptive.run_sequence(ctx, B, be, orbs, fp64_below_level=below, fp64_check=True)
     for r in recs:
         log(f"it {r['iteration']:2d} level {r['level']} s {r['slices']} {r['ms']:.2f} ms "
             f"E {r['energy']:.12f} dE(fp64) {r['energy_err']:.2e}")
@@ -238,10 +238,10 @@ def controller_workload(args):
     ctx.df_density(orbs[0], 2.0, D)
     times, below = adaptive.calibrate(ctx, B, be, orbs[0], 2.0, D, J, K, en, eb)
     log(f"controller: calibration ms {times}, FP64 from level {below} down")
-    plain = adaptive.run_sequence(ctx, B, be, orbs, fp64_below_level=below, judge=True)
+    plain = adaptive.run_sequence(ctx, B, be, orbs, fp64_below_level=below, fp64_check=True)
     # the controller takes the plain run's reference count in every iteration, so the
     # two are compared at the same reference accuracy
-    ctl = controller.run_controlled(ctx, B, be, orbs, params, fp64_below_level=below, judge=True,
+    ctl = controller.run_controlled(ctx, B, be, orbs, params, fp64_below_level=below, fp64_check=True,
                                     s_refs=[r["slices"] for r in plain])
     nb = (naux + 63) // 64
     w_plain = sum(nb * r["slices"] * (r["slices"] + 1) // 2 for r in plain)

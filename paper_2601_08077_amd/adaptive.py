@@ -40,11 +40,11 @@ def calibrate(ctx, B, b_exp, C, occ, D, J, K, energies, err_bound, reps=3):
     return times, below
 
 
-def run_sequence(ctx, B, b_exp, orbitals, occ=2.0, fp64_below_level=0, judge=False):
+def run_sequence(ctx, B, b_exp, orbitals, occ=2.0, fp64_below_level=0, fp64_check=False):
     """Run the builds for a list of device orbital matrices C_k.
 
     Returns a list of per-iteration records (level, slices, E_J, E_x, E, ms,
-    err_bound and, with ``judge``, the error of K against the FP64 build of
+    err_bound and, with ``fp64_check``, the error of K against the FP64 build of
     the same density)."""
     import torch
     naux, nao = B.shape[0], B.shape[1]
@@ -53,7 +53,7 @@ def run_sequence(ctx, B, b_exp, orbitals, occ=2.0, fp64_below_level=0, judge=Fal
     D = torch.empty((nao, nao), dtype=torch.float64, device=dev)
     J = torch.empty_like(D)
     K = torch.empty_like(D)
-    K64 = torch.empty_like(D) if judge else None
+    K64 = torch.empty_like(D) if fp64_check else None
     en = torch.empty(2, dtype=torch.float64, device=dev)
     eb = torch.empty(1, dtype=torch.float64, device=dev)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -72,7 +72,7 @@ def run_sequence(ctx, B, b_exp, orbitals, occ=2.0, fp64_below_level=0, judge=Fal
         ms = ev0.elapsed_time(ev1)
         rec = dict(iteration=k, level=level, slices=s, e_j=float(e[0]), e_x=float(e[1]),
                    energy=float(e[0] + e[1]), ms=ms, err_bound=float(eb.cpu()[0]))
-        if judge:
+        if fp64_check:
             ctx.df_set_precision(0)
             en64 = torch.empty_like(en)
             ctx.df_build_jk(B, b_exp, Ck, occ, D, J, K64, en64, eb)

@@ -181,7 +181,7 @@ def evaluate(ctx, params, x, t, m):
 
 
 def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below_level=0,
-                   spot=2, margin=1.0, decay=0.9, judge=False, seed=0, s_refs=None):
+                   spot=2, margin=1.0, decay=0.9, fp64_check=False, seed=0, s_refs=None):
     """The controlled sequence.  Per iteration: plain-rule reference count,
     features, prediction, per-block allocation, build, FP64 spot check (and
     fallback to the uniform reference count).  Returns per-iteration records
@@ -201,8 +201,8 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
     spot_err = torch.empty(max(spot, 1), dtype=torch.float64, device=B.device)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    K64 = torch.empty_like(b.K) if judge else None
-    en64 = torch.empty_like(b.en) if judge else None
+    K64 = torch.empty_like(b.K) if fp64_check else None
+    en64 = torch.empty_like(b.en) if fp64_check else None
     level, e_prev, e_prev2 = 4, None, None
     corr = np.zeros(8)  # per-s correction of the predictions (decades, >= 0)
     recs = []
@@ -257,7 +257,7 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
                    work=int(sum(s * (s + 1) // 2 for s in sb)),
                    work_ref=int(nb * s_ref * (s_ref + 1) // 2), energy=e_now, ms=ms,
                    err_bound=float(b.eb.cpu()[0]))
-        if judge:
+        if fp64_check:
             ctx.df_set_block_precision([0] * nb)
             ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, K64, en64, b.eb)
             nrm = float(torch.linalg.norm(K64))

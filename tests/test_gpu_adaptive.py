@@ -44,7 +44,7 @@ def test_sequence_follows_rule_and_oracle(ctx):
     B = torch.from_numpy(p["B"]).cuda()
     be = torch.empty(naux * nao, dtype=torch.int32, device="cuda")
     ctx.df_b_exponents(B, be)
-    recs = adaptive.run_sequence(ctx, B, be, [torch.from_numpy(c).cuda() for c in orbs], judge=True)
+    recs = adaptive.run_sequence(ctx, B, be, [torch.from_numpy(c).cuda() for c in orbs], fp64_check=True)
     energies = [r["energy"] for r in recs]
     expect = rule.schedule(energies)[:len(recs)]
     assert [r["slices"] for r in recs] == expect

@@ -56,8 +56,8 @@ def test_trained_controller_beats_plain_rule(torch_dev):
     ctx.df_set_block_precision(None)
     ctx.df_set_pblk(64)
     ctx.ensure_workspace(NAUX, NAO, NOCC)
-    plain = adaptive.run_sequence(ctx, B, be, orbs, judge=True)
-    ctl = controller.run_controlled(ctx, B, be, orbs, params, judge=True, spot=2)
+    plain = adaptive.run_sequence(ctx, B, be, orbs, fp64_check=True)
+    ctl = controller.run_controlled(ctx, B, be, orbs, params, fp64_check=True, spot=2)
     nb = NAUX // 64
     w_plain = sum(nb * r["slices"] * (r["slices"] + 1) // 2 for r in plain)
     w_ctl = sum(r["work"] for r in ctl)
