@@ -135,8 +135,9 @@ int df_build_x(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t n
  *   b_exp   [naux*nao] from df_b_exponents, or NULL
  *   C       [nao][nocc];  occ the occupation factor (2 for closed shells)
  *   D       [nao][nao], the density occ * C C^T used for rho (Eq. 3); symmetric, like
- *           each B_P: when nao is a multiple of 64, rho sums the blocks on and below
- *           the diagonal of B_P o D, counting those below twice
+ *           each B_P: at 1..7 slices with nao a multiple of 64, rho sums the 64 x 64
+ *           blocks on and below the diagonal of B_P o D, those below counted twice
+ *           (the same sum in another rounding order)
  *   J, K    [nao][nao] outputs (both written in full, symmetric)
  *   energies[2] output: E_J, E_x
  *   err_bound[1] output: an upper bound on max |K - K_exact| (absolute) that
