@@ -211,7 +211,21 @@ __global__ void k_bound_prep(const int32_t* __restrict__ b_exp, const int32_t* _
     const int64_t p1 = p0 + pblk < naux ? p0 + pblk : naux;
     const double k1 = sblk ? kappa_of(sblk[b], nao) : kappa1;
     double se = 0.0, me = 0.0;
-    for (int64_t P = p0; P < p1; ++P) {
+    // eight independent exponent loads in flight per step (the sum order is
+    // unchanged: P ascending)
+    int64_t P = p0;
+    for (; P + 8 <= p1; P += 8) {
+      int ex[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ex[u] = b_exp[(P + u) * nao + mu];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double v = ldexp(1.0, ex[u]);
+        se += v;
+        me = fmax(me, v);
+      }
+    }
+    for (; P < p1; ++P) {
       const double v = ldexp(1.0, b_exp[P * nao + mu]);
       se += v;
       me = fmax(me, v);
