@@ -327,9 +327,10 @@ __global__ __launch_bounds__(512) void k_x_int8(
     // issue the loads of chunk cnn (after the copies, in this order), multiply
     // chunk c and meet at the barrier.  Full K: the barrier is written out
     // (s_waitcnt + s_barrier, a compiler memory barrier) and waits only for
-    // this wave's copies and LDS stores: the loads of chunk cnn, exactly 8
-    // vector-memory operations issued after the copies, stay in flight into
-    // the next step.  Ragged K: a workgroup barrier (waits for everything).
+    // this wave's copies and LDS stores: the loads of chunk cnn, the only
+    // vector-memory operations issued after the copies (8, or 4 when chunk cnn
+    // is past the diagonal block and its D rows are not read), stay in flight
+    // into the next step.  Ragged K: a workgroup barrier (waits for everything).
     static_assert(NV == 8, "two-stage X loop assumes 8 values per lane and chunk");
 #define DFJK_X_STEP(BB)                                                                         \
   {                                                                                             \
