@@ -246,13 +246,17 @@ __global__ __launch_bounds__(512) void k_x_int8(
     }                                                                                      \
   }
   // C digits of chunk CC straight into LDS stage BUF (two-stage loop only).
+  // A wave with no block left in the last round skips it (wave-uniform; the
+  // barrier's count concerns only the loads issued after the copies).
+  const int wcu = __builtin_amdgcn_readfirstlane(w);
 #define DFJK_X_CDMA(BUF, CC)                                                                \
   _Pragma("unroll") for (int j = 0; j < CIW; ++j) {                                        \
-    const int ins = w + 8 * j;                                                             \
-    /* block ins: plane a, columns col0 .. col0 + 15 (spare rows past the last) */        \
-    const int row0 = ins < CINS ? (ins * 64) / 4 : S * NT;                                 \
-    int8_t* dst = &DFJK_CSB(BUF)[row0][0];                                                  \
-    copy16_to_lds(crsrc, dst, coff[j], (CC) * ncp * 64);                                   \
+    const int ins = wcu + 8 * j;                                                           \
+    /* block ins: plane a, columns col0 .. col0 + 15 */                                    \
+    if (j + 1 < CIW || ins < CINS) {                                                       \
+      int8_t* dst = &DFJK_CSB(BUF)[(ins * 64) / 4][0];                                      \
+      copy16_to_lds(crsrc, dst, coff[j], (CC) * ncp * 64);                                 \
+    }                                                                                      \
   }
 
   // Digits of chunk CC, whose B values and C digits sit in registers, into
