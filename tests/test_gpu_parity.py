@@ -120,6 +120,7 @@ SHAPES = [
     (70, 100, 33, 16, True),
     (130, 65, 100, 64, True),
     (1, 1, 1, 64, False),
+    (128, 70, 40, 64, True),         # nao a multiple of 64: the two-stage X path, two mu blocks
 ]
 
 
