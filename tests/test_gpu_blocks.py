@@ -58,6 +58,7 @@ CASES = [  # nao, naux, nocc, pblk, s per block
     (70, 100, 33, 16, [1, 2, 3, 4, 5, 6, 8]),
     (96, 384, 16, 64, [8, 8, 3, 3, 3, 6]),
     (130, 65, 100, 64, [4, 2]),
+    (128, 130, 24, 64, [5, 3, 7]),   # nao a multiple of 64: the two-stage X path
 ]
 
 
