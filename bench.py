@@ -38,21 +38,29 @@ def flops_paper(nao, naux, nocc, nscr=None):
 
 
 def stage_units(stage, s, nao, naux, nocc):
-    """Algorithmic (ops, bytes) of one launch of a stage; ops are INT8 ops for s >= 1.
+    """Algorithmic (ops, bytes) of one launch of a stage (what the method must
+    compute and move, not what this implementation happens to move); ops are
+    INT8 ops for s >= 1 (the s(s+1)/2 digit products), FP64 flops for s = 0.
 
-    x: the B.C products (and the B.D row dots of rho, fused) read B once and
-    write X; k: the symmetric products read the digits of X (FP64 X for s = 0);
-    rho: the sum of the row dots; j: the lower triangle of B once."""
+    x: X = B C over the stored B (the lower triangle, read once; the B.D row
+       dots of rho ride on the same read) plus C; X itself is a streamed
+       workspace, so no X round trip is counted;
+    slice_x: X read once, its s digit planes written once;
+    k: the symmetric products over the digits of X (FP64 X for s = 0), read once;
+    rho: the row dots summed;
+    j: the stored B read once."""
     npairs = s * (s + 1) // 2 if s else 1
     nn = nao * nao
+    ntri = nao * (nao + 1) // 2
     if stage == "x":
-        return npairs * 2 * naux * nn * nocc, 8 * naux * nn + 8 * naux * nao * nocc
+        return npairs * 2 * naux * nn * nocc, 8 * naux * ntri + 8 * nao * nocc
+    if stage == "slice_x":
+        return 0, (8 + s) * naux * nao * nocc if s else 0
     if stage == "k":
         return npairs * nao * (nao + 1) * naux * nocc, (s if s else 8) * naux * nao * nocc
     if stage == "rho":
         return naux * nao, 8 * naux * nao
     if stage == "j":
-        ntri = nao * (nao + 1) // 2
         return 2 * naux * ntri, 8 * naux * ntri
     return 0, 0
 
@@ -83,21 +91,52 @@ def measured_traffic(stage, s):
     return None
 
 
-def roofline_of(stage, ms, s, nao, naux, nocc):
+def roofline_of(stage, ms, s, nao, naux, nocc, measured=None):
+    """Roofline record of one stage: the binding roof is the larger of the
+    algorithmic ops at the compute peak and the algorithmic bytes at the HBM
+    peak (datasheet peaks; the measured ones are reported beside them)."""
     ops, byts = stage_units(stage, s, nao, naux, nocc)
-    comp_peak = PEAK["int8"] if s else PEAK["fp64"]
+    comp_key = "int8" if s else "fp64"
+    comp_peak = PEAK[comp_key]
     t_comp = ops / (comp_peak * 1e12)
     t_mem = byts / (PEAK["hbm"] * 1e9)
     sec = ms * 1e-3
+    traffic = measured_traffic(stage, s)
+    rec = {"kernel": stage, "launch_ms": ms, "ops_per_launch": ops,
+           "ops_kind": "int8 ops" if s else "fp64 flops", "bytes_per_launch": byts,
+           "traffic": traffic,
+           "traffic_over_algorithmic": (traffic / byts) if (traffic and byts) else None,
+           "t_ops_at_peak_ms": t_comp * 1e3, "t_bytes_at_peak_ms": t_mem * 1e3}
     if t_comp >= t_mem:
         ach = ops / sec / 1e12
-        return {"bound": "mfma", "achieved": ach, "peak": comp_peak, "unit": "TFLOP/s",
-                "frac": ach / comp_peak, "traffic": measured_traffic(stage, s), "kernel": stage,
-                "ops_per_launch": ops, "ops_kind": "int8 ops" if s else "fp64 flops"}
-    ach = byts / sec / 1e9
-    return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
-            "frac": ach / PEAK["hbm"], "traffic": measured_traffic(stage, s), "kernel": stage,
-            "bytes_per_launch": byts}
+        rec.update({"bound": "mfma", "achieved": ach, "peak": comp_peak, "unit": "TFLOP/s",
+                    "frac": ach / comp_peak})
+        if measured and measured.get(comp_key):
+            rec["frac_of_measured_peak"] = ach / measured[comp_key]
+    else:
+        ach = byts / sec / 1e9
+        rec.update({"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s",
+                    "frac": ach / PEAK["hbm"]})
+        if measured and measured.get("read"):
+            rec["frac_of_measured_peak"] = ach / measured["read"]
+    return rec
+
+
+def measured_peaks(ctx):
+    """The device's own peak probes: INT8 and FP64 MFMA loops, HBM copy and read."""
+    import torch
+    out = {}
+    buf = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
+    out["int8"] = ctx.df_peak_probe(0, buf, iters=4000)
+    out["fp64"] = ctx.df_peak_probe(1, buf, iters=1000)
+    out["copy"] = ctx.df_peak_probe(2, buf)
+    out["read"] = ctx.df_peak_probe(3, buf)
+    del buf
+    torch.cuda.synchronize()
+    return {"int8": out["int8"], "fp64": out["fp64"], "copy": out["copy"], "read": out["read"],
+            "units": {"int8": "TOP/s", "fp64": "TFLOP/s", "copy": "GB/s (read + written)",
+                      "read": "GB/s"},
+            "datasheet": {"int8": PEAK["int8"], "fp64": PEAK["fp64"], "hbm": PEAK["hbm"]}}
 
 
 def cpu_baseline(s, naux_sample, nao, nocc, L):
@@ -533,10 +572,15 @@ def main():
            "bound_abs": float(eb[0]), "bound_rel_fro": float(eb[0]) / nK,
            "reference": "the same build in native FP64 MFMA on the GPU (agrees with the CPU "
                         "oracle to FP64 rounding in the parity tests)"}
-    dom = max(("x", "k", "rho", "j"), key=lambda k: st[k])
-    roof = roofline_of(dom, st[dom], s, nao, naux, nocc)
-    roof["launch_ms"] = st[dom]
-    others = {k: roofline_of(k, st[k], s, nao, naux, nocc) for k in ("x", "k", "rho", "j")}
+    log("peak probes")
+    peaks = measured_peaks(ctx)
+    log(f"peaks: INT8 {peaks['int8']:.0f} TOP/s, FP64 {peaks['fp64']:.1f} TFLOP/s, "
+        f"copy {peaks['copy']:.0f} GB/s, read {peaks['read']:.0f} GB/s")
+    stages = ("x", "slice_x", "k", "rho", "j")
+    dom = max(stages, key=lambda k: st[k])
+    roof = roofline_of(dom, st[dom], s, nao, naux, nocc, peaks)
+    others = {k: roofline_of(k, st[k], s, nao, naux, nocc, peaks) for k in stages}
+    others64 = {k: roofline_of(k, st64[k], 0, nao, naux, nocc, peaks) for k in ("x", "k", "j")}
 
     out = {
         "metric": METRIC,
@@ -563,6 +607,8 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in st.items()},
         "roofline": roof,
         "roofline_stages": others,
+        "roofline_stages_fp64": others64,
+        "peaks_measured": peaks,
         "sweep": sweep,
         "sliced_mode": {"prepare_b_ms": sliced_prep_ms, "planes": 8, "levels": sliced},
     }

@@ -80,7 +80,7 @@ int df_get_precision(const df_ctx* ctx);
 
 /* Per-aux-block slice counts for df_build_jk (the learned controller's
  * decisions; per-block precision extends the per-iteration rule of Sec. 3.2,
- * Table 1, in the direction of Sec. 6): host_s[b] in 0..8 for each of the
+ * Table 1, in the direction of Sec. 5): host_s[b] in 0..8 for each of the
  * nblocks = ceil(naux / pblk) aux blocks, 0 = native FP64 for that block.
  * X_b and K_b of block b are then formed at host_s[b]; each block gets its
  * own K partial (the K group count becomes nblocks), summed in ascending
@@ -103,6 +103,13 @@ int df_set_pblk(df_ctx* ctx, int pblk);
  * ascending order, so the emulated K is deterministic for a given value. */
 int df_set_k_groups(df_ctx* ctx, int groups);
 int df_get_k_groups(const df_ctx* ctx);
+
+/* Depth of the nu chunk that one step of the INT8 X product stages in LDS:
+ * 1 = 64 (two LDS stages, the default), 2 = 128 (one stage; used only where
+ * slices <= 5 and nao is a multiple of 128, else 64), 0 = the autotuned choice
+ * of df_autotune for the shape, else the default.  Results are identical at
+ * every depth (the int32 sums are exact).  DF_EINVAL outside 0..2. */
+int df_set_x_ksub(df_ctx* ctx, int ksub);
 
 /* Bytes of device workspace needed by df_build_jk / df_build_x for this shape
  * at any precision.  The caller allocates it and hands it over with
@@ -278,7 +285,7 @@ int df_rule_next_level(int level, double e_prev, double e_now);
 int df_rule_slices(int level, int fp64_below_level);
 
 /* ---- Learned slice controller (per-aux-block precision; extends the
- * per-iteration rule of Sec. 3.2 / Table 1 along the outlook of Sec. 6) ----
+ * per-iteration rule of Sec. 3.2 / Table 1 along the outlook of Sec. 5) ----
  * The context owns an 8 MiB device scratch for these calls (allocated by
  * df_create); calls on one context are ordered by its stream.
  *
@@ -384,13 +391,45 @@ enum df_stage {
 int df_timing_begin(df_ctx* ctx, int max_calls);
 int df_timing_end(df_ctx* ctx, double* ms_sum, int* ncalls);
 
-/* Test hook: the exact int32 products of every kept slice pair, as formed by
- * the INT8 MFMA tiles of the emulated products.  a_dig [s][m][k] and
- * b_dig [s][k][n] are int8 digit planes; partials[p][m][n] receives
+/* Peak probes of the device (the denominators of roofline fractions, measured
+ * here instead of taken from a datasheet).  Runs one warm-up and three timed
+ * launches of one probe on the context stream (synchronises; creates and
+ * destroys two HIP events) and writes the rate to *rate (host):
+ *   kind 0: INT8 MFMA loop (v_mfma_i32_16x16x64_i8, 8 independent chains per
+ *           wave, 32 waves per CU, `iters` trips): TOP/s;
+ *   kind 1: FP64 MFMA loop (v_mfma_f64_16x16x4_f64, same shape): TFLOP/s;
+ *   kind 2: streaming copy of bytes / 2 into the second half of buf: GB/s of
+ *           bytes read plus bytes written;
+ *   kind 3: streaming read of buf: GB/s read.
+ * buf: caller-owned device memory, 256-byte aligned; kinds 0/1 need
+ * CUs x 16 KiB (scratch for the chain sums), kinds 2/3 at least 4 MiB (use
+ * far more than the caches hold, e.g. 4 GiB).  iters 1..10^6 (kinds 2/3 ignore
+ * it).  Contents of buf are overwritten. */
+int df_peak_probe(df_ctx* ctx, int kind, void* buf, size_t bytes, int iters, double* rate);
+
+/* Test hooks.
+ * df_debug_build_i32: the int32 sums of the hot path itself.  Runs the INT8 X
+ * and K kernels of df_build_jk at the context precision s >= 1 (uniform, no
+ * per-block counts; same arguments as df_build_jk's X inputs, workspace of
+ * df_workspace_size) and exports, before recombination,
+ *   x_sums[g-2][P*nao + mu][i] = S_g of row (P, mu) of B and column i of C,
+ *     the sum over the pairs a + b = g (g = 2..s+1) of the digit products
+ *     (Sec. 3.2, Eq. 8), as accumulated by the X tiles;
+ *   k_sums[g-2][b][mu][nu] = S_g of rows mu and nu of X_b (aux block b of
+ *     pblk indices, nb = ceil(naux / pblk) blocks), as accumulated by the K
+ *     tiles; written only where mu / 64 >= nu / 64 (the lower 64 x 64 tiles
+ *     the K kernel forms).
+ * df_debug_slice_gemm_i32: the exact int32 product of every kept slice pair of
+ * given digit planes, formed by a plain kernel on the same MFMA instruction
+ * (v_mfma_i32_16x16x64_i8; not the tiles of the hot path).  a_dig [s][m][k]
+ * and b_dig [s][k][n] are int8 digit planes; partials[p][m][n] receives
  * sum_k a_dig[a-1][.][k] * b_dig[b-1][k][.] for the p-th pair (a, b) in the
- * order a = 1..s, b = 1..s+1-a.  Needs k <= 131072 (single-pair int32 range)
- * and a workspace of at least s*M*Kp (rounded up to 256) + s*N*Kp bytes, with
+ * order a = 1..s, b = 1..s+1-a.  Needs k < 131072 (128^2 k < 2^31) and a
+ * workspace of at least s*M*Kp (rounded up to 256) + s*N*Kp bytes, with
  * M, N, Kp = m, n, k rounded up to multiples of 64. */
+int df_debug_build_i32(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t nao,
+                       const int32_t* b_exp, const double* C, int64_t nocc, int32_t* x_sums,
+                       int32_t* k_sums);
 int df_debug_slice_gemm_i32(df_ctx* ctx, const int8_t* a_dig, const int8_t* b_dig, int64_t m,
                             int64_t n, int64_t k, int s, int32_t* partials);
 

@@ -3,7 +3,7 @@ Adam (test infrastructure only).
 
 The paper picks one slice count per SCF iteration from the relative energy
 change (Sec. 3.2, Eq. 11, Table 1) and names, as future work, tying the
-precision to how the density matrix changes (Sec. 6).  The controller takes
+precision to how the density matrix changes (Sec. 5).  The controller takes
 that step per aux block: 16 features of a block and iteration go through a
 16 -> 64 -> 64 -> 8 perceptron (ReLU) whose 8 outputs predict
 log10(max |K_b(s) - K_b| / ||K||_F) for s = 1..8; the block gets the smallest

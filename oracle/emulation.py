@@ -347,30 +347,25 @@ def emulated_build_jk(B, C, s, occ=2.0, D=None, pblk=64, groups=1):
 # ----------------------------------------------------------------------------
 # Per-block slice counts (the learned controller's decisions)
 # ----------------------------------------------------------------------------
-def emulated_build_jk_blocks(B, C, s_blocks, occ=2.0, D=None, pblk=64):
-    """The emulated build with its own slice count s_b per aux block b (0 = FP64
-    for that block): X_b = emu(B_b C) at s_b, K_b = emu(X_b X_b^T) at s_b,
-    K = occ * sum_b K_b with b ascending; rho and J in FP64.  The K bound is
-    ``k_error_bound`` with each block's own factors.  Blocks with s_b = 0 use
-    NumPy's FP64 products (equal to a GPU FP64 product only up to rounding)."""
-    from . import jk as _jk
+def emulated_xk_blocks(B, C, s_blocks, occ=2.0, pblk=64):
+    """X and K with their own slice count s_b per aux block b (0 = FP64 for that
+    block): X_b = emu(B_b C) at s_b, K_b = emu(X_b X_b^T) at s_b,
+    K = occ * sum_b K_b with b ascending.  B may hold any subset of the rows
+    mu of every B_P (B[P, rows, nu]): X and K are then the same restriction of
+    the full results (every slicing exponent is per row).  Returns (X, K, F).
+    Blocks with s_b = 0 use NumPy's FP64 products (equal to a GPU FP64 product
+    only up to rounding)."""
     B = np.asarray(B, dtype=np.float64)
     C = np.asarray(C, dtype=np.float64)
-    naux, nao, _ = B.shape
+    naux, nrow, _ = B.shape
     nocc = C.shape[1]
     blocks = block_ranges(naux, pblk)
     s_blocks = [int(v) for v in s_blocks]
     if len(s_blocks) != len(blocks):
         raise ValueError("one slice count per aux block")
-    if D is None:
-        D = occ * (C @ C.T)
-    rho = _jk.rho_of(B, D)
-    J = _jk.j_of(B, rho)
-    X = np.zeros((naux, nao, nocc))
-    e_B = row_exponents(B.reshape(naux * nao, nao)).reshape(naux, nao)
-    f_C = row_exponents(C.T)
-    F = np.zeros((len(blocks), nao), dtype=np.int64)
-    Kacc = np.zeros((nao, nao))
+    X = np.zeros((naux, nrow, nocc))
+    F = np.zeros((len(blocks), nrow), dtype=np.int64)
+    Kacc = np.zeros((nrow, nrow))
     for bi, (p0, p1) in enumerate(blocks):
         sb = s_blocks[bi]
         if sb == 0:
@@ -385,9 +380,26 @@ def emulated_build_jk_blocks(B, C, s_blocks, occ=2.0, D=None, pblk=64):
             dX, _ = slice_rows(Xb, sb)
             Kb = recombine(slice_products(dX, dX.transpose(0, 2, 1), sb), F[bi], F[bi], sb)
         Kacc = Kacc + Kb
-    K = occ * Kacc
+    return X, occ * Kacc, F
+
+
+def emulated_build_jk_blocks(B, C, s_blocks, occ=2.0, D=None, pblk=64):
+    """The emulated build with its own slice count s_b per aux block b (0 = FP64
+    for that block): X and K as ``emulated_xk_blocks``; rho and J in FP64.  The
+    K bound is ``k_error_bound`` with each block's own factors."""
+    from . import jk as _jk
+    B = np.asarray(B, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    naux, nao, _ = B.shape
+    if D is None:
+        D = occ * (C @ C.T)
+    rho = _jk.rho_of(B, D)
+    J = _jk.j_of(B, rho)
+    e_B = row_exponents(B.reshape(naux * nao, nao)).reshape(naux, nao)
+    f_C = row_exponents(C.T)
+    X, K, F = emulated_xk_blocks(B, C, s_blocks, occ=occ, pblk=pblk)
     e_j, e_x = _jk.energies(rho, D, K)
-    bound = k_error_bound(e_B, f_C, F, s_blocks, occ=occ, pblk=pblk)
+    bound = k_error_bound(e_B, f_C, F, [int(v) for v in s_blocks], occ=occ, pblk=pblk)
     return dict(rho=rho, J=J, X=X, K=K, e_j=e_j, e_x=e_x, D=D, e_B=e_B, f_C=f_C, F=F,
                 bound=bound)
 

@@ -38,6 +38,7 @@ SIGNATURES = {
     "df_set_k_groups": (_int, [_c_void_p, _int]),
     "df_set_block_precision": (_int, [_c_void_p, ctypes.POINTER(ctypes.c_int32), _i64]),
     "df_get_k_groups": (_int, [_c_void_p]),
+    "df_set_x_ksub": (_int, [_c_void_p, _int]),
     "df_workspace_size": (_int, [_c_void_p, _i64, _i64, _i64, _int, ctypes.POINTER(ctypes.c_size_t)]),
     "df_set_workspace": (_int, [_c_void_p, _c_void_p, ctypes.c_size_t]),
     "df_b_exponents": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _c_void_p]),
@@ -87,8 +88,12 @@ SIGNATURES = {
     "df_rule_level": (_int, [ctypes.c_double]),
     "df_rule_next_level": (_int, [_int, ctypes.c_double, ctypes.c_double]),
     "df_rule_slices": (_int, [_int, _int]),
+    "df_peak_probe": (_int, [_c_void_p, _int, _c_void_p, ctypes.c_size_t, _int,
+                             ctypes.POINTER(ctypes.c_double)]),
     "df_timing_begin": (_int, [_c_void_p, _int]),
     "df_timing_end": (_int, [_c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_int)]),
+    "df_debug_build_i32": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _c_void_p, _c_void_p,
+                                  _i64, _c_void_p, _c_void_p]),
     "df_debug_slice_gemm_i32": (_int, [_c_void_p, _c_void_p, _c_void_p, _i64, _i64, _i64, _int,
                                        _c_void_p]),
 }
@@ -179,6 +184,9 @@ class Context:
         arr = (ctypes.c_int32 * len(s_blocks))(*[int(v) for v in s_blocks])
         self._check(self.lib.df_set_block_precision(self.h, arr, len(s_blocks)),
                     "df_set_block_precision")
+
+    def df_set_x_ksub(self, ksub):
+        self._check(self.lib.df_set_x_ksub(self.h, int(ksub)), "df_set_x_ksub")
 
     def df_get_k_groups(self):
         return self.lib.df_get_k_groups(self.h)
@@ -344,6 +352,14 @@ class Context:
         self._check(self.lib.df_density(self.h, _ptr(C), C.shape[0], C.shape[1], float(occ), _ptr(D)),
                     "df_density")
 
+    def df_peak_probe(self, kind, buf, iters=1):
+        """Rate of peak probe `kind` (0 INT8 MFMA TOP/s, 1 FP64 MFMA TFLOP/s,
+        2 copy GB/s, 3 read GB/s) on the uint8 device tensor buf."""
+        r = ctypes.c_double()
+        self._check(self.lib.df_peak_probe(self.h, int(kind), _ptr(buf), buf.numel(), int(iters),
+                                           ctypes.byref(r)), "df_peak_probe")
+        return r.value
+
     def df_timing_begin(self, max_calls):
         self._check(self.lib.df_timing_begin(self.h, int(max_calls)), "df_timing_begin")
 
@@ -356,6 +372,13 @@ class Context:
 
     def df_get_status(self):
         return self.lib.df_get_status(self.h)
+
+    def df_debug_build_i32(self, B, b_exp, C, x_sums, k_sums, layout=DF_DENSE):
+        """x_sums int32 [s][naux*nao][nocc], k_sums int32 [s][nb][nao][nao]."""
+        naux, nao = B.shape[0], B.shape[1]
+        self._check(self.lib.df_debug_build_i32(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp),
+                                                _ptr(C), C.shape[1], _ptr(x_sums), _ptr(k_sums)),
+                    "df_debug_build_i32")
 
     def df_debug_slice_gemm_i32(self, a_dig, b_dig, s, partials):
         _, m, k = a_dig.shape

@@ -15,16 +15,21 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdfjk.so")
-SOURCES = ["api.hip", "slicing.hip", "int8_gemm.hip", "fp64_gemm.hip", "jk.hip", "metric.hip", "sliced.hip", "controller.hip", "screen.hip"]
+SOURCES = ["api.hip", "slicing.hip", "int8_gemm.hip", "fp64_gemm.hip", "jk.hip", "metric.hip", "sliced.hip", "controller.hip", "screen.hip", "peak.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 GPU_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", os.path.join(ROOT, "include")]
 
 
+# Per-file flags: the peak probes keep their MFMA accumulators in VGPRs (the
+# default register form copies them between AGPRs and VGPRs every loop trip).
+EXTRA = {"peak.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *GPU_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *GPU_FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")

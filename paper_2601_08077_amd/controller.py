@@ -1,5 +1,5 @@
 """Learned per-block slice controller (the per-iteration rule of Sec. 3.2 /
-Table 1 taken down to aux blocks, along the outlook of Sec. 6).
+Table 1 taken down to aux blocks, along the outlook of Sec. 5).
 
 Sample generation, GPU training and the controlled sequence of J/K builds.
 Every numerical step runs in libdfjk: block statistics and features, the

@@ -19,6 +19,7 @@ struct df_ctx {
   int pblk = 64;
   int k_groups_req = 0;
   int k_groups_used = 0;
+  int x_ksub_req = 0;  // X chunk depth asked for (0 = autotuned or default)
   int ncu = 256;  // compute units of the context's device
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -200,8 +201,10 @@ T* at(df_ctx* c, size_t off) {
   return reinterpret_cast<T*>(c->ws + off);
 }
 
-// Autotuned X chunk depth for this shape at the context precision (0 = default).
+// X chunk depth: the one set by df_set_x_ksub, else the autotuned one for
+// this shape at the context precision, else 0 (the default).
 int ksub_for(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
+  if (c->x_ksub_req) return c->x_ksub_req;
   const auto it = c->tuned.find(std::make_tuple(naux, nao, nocc, c->slices, c->pblk));
   return it != c->tuned.end() ? it->second.second : 0;
 }
@@ -244,7 +247,8 @@ int run_x(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp, const
   DF_HIP(launch_col_exp(c->stream, C, p.nao, p.nocc, fcol, c->status), "col_exp");
   DF_HIP(launch_slice_c(c->stream, C, p.nao, p.nocc, s, fcol, p.ncp, p.kp, 0, dC), "slice_c");
   DF_HIP(launch_x_int8(c->stream, s, B, p.naux, (int)p.nao, b_exp, dC, p.ncp, p.kp, fcol,
-                       (int)p.nocc, X, 0, xmax, p.pblk, nullptr, nullptr, chunks_for(c, p.nao)),
+                       (int)p.nocc, X, 0, xmax, p.pblk, nullptr, nullptr, chunks_for(c, p.nao),
+                       ksub_for(c, p.naux, p.nao, p.nocc)),
          "x_int8");
   return DF_OK;
 }
@@ -508,6 +512,13 @@ int df_set_block_precision(df_ctx* c, const int32_t* host_s, int64_t nblocks) {
 }
 
 int df_get_k_groups(const df_ctx* c) { return c ? c->k_groups_used : DF_EINVAL; }
+
+int df_set_x_ksub(df_ctx* c, int ksub) {
+  if (!c) return DF_EINVAL;
+  if (ksub < 0 || ksub > 2) return fail(c, DF_EINVAL, "ksub must be 0, 1 or 2");
+  c->x_ksub_req = ksub;
+  return DF_OK;
+}
 
 int df_workspace_size(df_ctx* c, int64_t naux, int64_t nao, int64_t nocc, int layout,
                       size_t* bytes) {
@@ -940,8 +951,9 @@ int df_autotune(df_ctx* c, const double* B, const int32_t* b_exp, int64_t naux, 
   if (!c->blk_s.empty()) return fail(c, DF_EINVAL, "autotuning needs uniform precision");
   const auto key = std::make_tuple(naux, nao, nocc, c->slices, c->pblk);
   c->tuned.erase(key);
-  const int saved_req = c->k_groups_req;
+  const int saved_req = c->k_groups_req, saved_ksub = c->x_ksub_req;
   c->k_groups_req = 0;
+  c->x_ksub_req = 0;
   const Plan base = make_plan(c, naux, nao, nocc);
   std::vector<int> groups = {base.groups};
   for (int g = 1; g <= std::min(base.nb, 64); g *= 2)
@@ -981,6 +993,7 @@ int df_autotune(df_ctx* c, const double* B, const int32_t* b_exp, int64_t naux, 
   }
   c->ev_cap = saved_cap;
   c->k_groups_req = saved_req;
+  c->x_ksub_req = saved_ksub;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) {
@@ -1136,6 +1149,39 @@ int df_build_jk_batched(df_ctx* c, int n, const df_problem* probs, int streams) 
   c->scr_blk = saved_blk;
   c->scr_nao = saved_nao;
   return rc;
+}
+
+int df_peak_probe(df_ctx* c, int kind, void* buf, size_t bytes, int iters, double* rate) {
+  clear_stale_error();
+  if (!c) return DF_EINVAL;
+  if (kind < 0 || kind > 3 || !buf || !rate) return fail(c, DF_EINVAL, "bad kind, buffer or rate");
+  if (reinterpret_cast<uintptr_t>(buf) & 255) return fail(c, DF_EINVAL, "buffer must be 256-byte aligned");
+  if (iters < 1 || iters > 1000000) return fail(c, DF_EINVAL, "iters must be 1..10^6");
+  const size_t need = kind <= 1 ? (size_t)c->ncu * 8 * 256 * 8 : (size_t)1 << 22;
+  if (bytes < need) return fail(c, DF_EINVAL, "buffer too small for this probe");
+  hipEvent_t e0, e1;
+  DF_HIP(hipEventCreate(&e0), "hipEventCreate");
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(c, e, "hipEventCreate");
+  }
+  double work = 0.0;
+  constexpr int kReps = 3;
+  e = launch_peak(c->stream, kind, c->ncu, buf, bytes, iters, &work);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+  for (int r = 0; r < kReps && e == hipSuccess; ++r)
+    e = launch_peak(c->stream, kind, c->ncu, buf, bytes, iters, &work);
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(c, e, "peak probe");
+  // TOP/s, TFLOP/s or GB/s
+  *rate = kind <= 1 ? work * kReps / (ms * 1e-3) / 1e12 : work * kReps / (ms * 1e-3) / 1e9;
+  return DF_OK;
 }
 
 int df_timing_begin(df_ctx* c, int max_calls) {
@@ -1295,13 +1341,51 @@ int df_get_status(df_ctx* c) {
 
 const char* df_last_error(const df_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+int df_debug_build_i32(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao,
+                       const int32_t* b_exp, const double* C, int64_t nocc, int32_t* x_sums,
+                       int32_t* k_sums) {
+  clear_stale_error();
+  Plan p;
+  int rc = common_checks(c, B, layout, naux, nao, C, nocc, p);
+  if (rc) return rc;
+  if (!x_sums || !k_sums) return fail(c, DF_EINVAL, "null output");
+  if (!c->blk_s.empty()) return fail(c, DF_EINVAL, "the export uses one slice count: reset block precision");
+  const int s = c->slices;
+  if (s < 1) return fail(c, DF_EINVAL, "the export needs 1..8 slices");
+  hipStream_t st = c->stream;
+  if (!b_exp) {
+    int32_t* be = at<int32_t>(c, p.off_bexp);
+    DF_HIP(launch_row_exp(st, B, naux * nao, nao, nao, be, c->status), "row_exp");
+    b_exp = be;
+  }
+  double* X = at<double>(c, p.off_X);
+  int32_t* fcol = at<int32_t>(c, p.off_fcol);
+  int8_t* dC = at<int8_t>(c, p.off_dC);
+  unsigned long long* xmax = at<unsigned long long>(c, p.off_xmax);
+  DF_HIP(launch_fill_u64(st, xmax, (int64_t)p.nb * p.nao, 0ull), "fill xmax");
+  DF_HIP(launch_col_exp(st, C, nao, nocc, fcol, c->status), "col_exp");
+  DF_HIP(launch_slice_c(st, C, nao, nocc, s, fcol, p.ncp, p.kp, 0, dC), "slice_c");
+  DF_HIP(launch_x_int8(st, s, B, naux, (int)nao, b_exp, dC, p.ncp, p.kp, fcol, (int)nocc, X, 1,
+                       xmax, p.pblk, nullptr, nullptr, chunks_for(c, nao),
+                       ksub_for(c, naux, nao, nocc), x_sums),
+         "x_int8");
+  int32_t* F = at<int32_t>(c, p.off_F);
+  int8_t* Xd = at<int8_t>(c, p.off_Xd);
+  DF_HIP(launch_slice_x(st, s, X, naux, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp, xmax, F, Xd),
+         "slice_x");
+  DF_HIP(launch_k_int8(st, s, Xd, F, p.nb, (int)nao, p.nao_pad, p.kbp, p.groups,
+                       at<double>(c, p.off_Kp), k_sums),
+         "k_int8");
+  return DF_OK;
+}
+
 int df_debug_slice_gemm_i32(df_ctx* c, const int8_t* a_dig, const int8_t* b_dig, int64_t m,
                             int64_t n, int64_t k, int s, int32_t* partials) {
   clear_stale_error();
   if (!c) return DF_EINVAL;
   if (!a_dig || !b_dig || !partials) return fail(c, DF_EINVAL, "null pointer");
   if (m < 1 || n < 1 || k < 1 || s < 1 || s > kMaxSlices) return fail(c, DF_EINVAL, "bad shape");
-  if (k > 131072) return fail(c, DF_EOVERFLOW_GUARD, "k > 131072");
+  if (k >= 131072) return fail(c, DF_EOVERFLOW_GUARD, "k >= 131072: 128^2 k reaches 2^31");
   const int64_t mp = round_up(m, 64), np = round_up(n, 64), kpd = round_up(k, 64);
   const size_t need_a = (size_t)s * mp * kpd, need_b = (size_t)s * np * kpd;
   const size_t need = (need_a + 255) / 256 * 256 + need_b;

@@ -2,7 +2,7 @@
 // 16 -> 64 -> 64 -> 8 perceptron (FP32: forward, backward, Adam), the slice
 // choice and the FP64 check of emulated block partials.  The controller
 // extends the per-iteration precision rule (Sec. 3.2, Eq. 11, Table 1) to one
-// slice count per aux block, following the outlook of Sec. 6.
+// slice count per aux block, following the outlook of Sec. 5.
 #include "dfjk_internal.h"
 
 namespace dfjk {

@@ -11,6 +11,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 namespace dfjk {
 
 constexpr int kWave = 64;
+// LDS one gfx950 workgroup may allocate (bytes); every kernel with a large
+// static LDS footprint checks it at compile time.  No launch uses dynamic LDS.
+constexpr int kLdsLimit = 160 * 1024;
 constexpr int kMaxSlices = 8;
 constexpr int kStatusNonFinite = 1;
 constexpr int kStatusNotSpd = 2;
@@ -154,17 +157,22 @@ hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, i
                          const int32_t* b_exp, const int8_t* dC, int ncp, int kp,
                          const int32_t* f_col, int nocc, double* X, int xlayout,
                          unsigned long long* xmax, int pblk, const double* D, double* rowdot,
-                         const unsigned long long* cmask = nullptr, int ksub = 0);
+                         const unsigned long long* cmask = nullptr, int ksub = 0,
+                         int32_t* dbg = nullptr);
 // (ksub: k depth per LDS stage, 1 = 64, 2 = 128 where s <= 5 and nao % 128 == 0,
-// 0 = the default choice.)
+// 0 = the default choice.  dbg, a test export: [s][naux*nao][nocc] int32
+// anti-diagonal sums g = 2..s+1 of the tiles.)
 // X in the blocked layout.
 hipError_t launch_slice_x(hipStream_t st, int s, const double* Xb, int64_t naux, int nao,
                           int nocc, int pblk, int nao_pad, int kbp,
                           const unsigned long long* xmax, int32_t* F, int8_t* Xd);
 // Workgroups of the INT8 K kernel for s slices that one CU holds at once.
 int k_int8_resident(int s);
+// dbg (test export, may be null): [s][nb][nao][nao] int32 anti-diagonal sums
+// per aux block, written where mu / 64 >= nu / 64 (the lower tiles).
 hipError_t launch_k_int8(hipStream_t st, int s, const int8_t* Xd, const int32_t* F, int nb,
-                         int nao, int nao_pad, int kbp, int groups, double* Kp);
+                         int nao, int nao_pad, int kbp, int groups, double* Kp,
+                         int32_t* dbg = nullptr);
 hipError_t launch_debug_pairs(hipStream_t st, int s, const int8_t* a_dig, const int8_t* b_dig,
                               int64_t m, int64_t n, int64_t k, int8_t* ws_a, int8_t* ws_b,
                               int32_t* partials);
@@ -237,6 +245,13 @@ hipError_t launch_j_dig(hipStream_t st, int s, const int8_t* Bd, int64_t bplane,
 hipError_t launch_screen(hipStream_t st, double* B, int64_t naux, int nao, int blk, double tau,
                          int nsplit, double* part, double* norms, uint8_t* mask,
                          unsigned long long* chunks);
+
+// peak.hip: device peak probes.  kind 0: INT8 MFMA loop, 1: FP64 MFMA loop
+// (iters loop trips; buf >= ncu * 8 * 256 * 8 bytes), 2: streaming copy of
+// bytes / 2 into the other half, 3: streaming read.  *work receives the ops
+// (0, 1) or bytes moved (2, 3) of the launch.
+hipError_t launch_peak(hipStream_t st, int kind, int ncu, void* buf, size_t bytes, int iters,
+                       double* work);
 
 // controller.hip (the per-block slice controller)
 struct CtlScalars {  // host scalars of one iteration, passed by value

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(512) void k_x_int8(
     const int8_t* __restrict__ dC, int ncp, int kp, const int32_t* __restrict__ f_col, int nocc,
     double* __restrict__ X, int xlayout, unsigned long long* __restrict__ xmax, int nao, int pblk,
     const double* __restrict__ D, double* __restrict__ rowdot,
-    const unsigned long long* __restrict__ cmask) {
+    const unsigned long long* __restrict__ cmask, int32_t* __restrict__ dbg) {
   constexpr int NT = 16 * NF, NFW = NF / 2;
   constexpr int KC = 64 * KSUB, ROW = KC;  // LDS rows: KC k bytes, units swizzled per 64 B
   constexpr int CUNITS = S * NT * 4 * KSUB;     // 16-byte units of C digits per chunk
@@ -111,6 +111,8 @@ __global__ __launch_bounds__(512) void k_x_int8(
   __shared__ __attribute__((aligned(16))) int8_t Cs0[S * NT + CPAD][ROW];
   __shared__ __attribute__((aligned(16))) int8_t Cs1[NBUF == 2 ? S * NT + CPAD : 1][ROW];
 #define DFJK_CSB(BUF) ((BUF) ? Cs1 : Cs0)
+  // (+ 8 bytes: the chunk mask of tile_chunks)
+  static_assert(sizeof(As) + sizeof(Cs0) + sizeof(Cs1) + 8 <= kLdsLimit, "X tile exceeds LDS");
 
   const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
   const int wrow = w & 3, half = w >> 2;  // waves w and w + 4 share 16 rows
@@ -410,6 +412,10 @@ __global__ __launch_bounds__(512) void k_x_int8(
         for (int g = S + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][f][r], base - 8 * g);
         xrow[col] = z;
         rmax = fmax(rmax, fabs(z));
+        if (dbg) {  // test export: the int32 anti-diagonal sums of this tile
+#pragma unroll
+          for (int g = 0; g < S; ++g) dbg[((int64_t)g * M + row) * nocc + col] = acc[g][f][r];
+        }
       }
     }
 #pragma unroll
@@ -498,11 +504,12 @@ __device__ __forceinline__ void lower_tile(int idx, int& t1, int& t2) {
 // 16 rows per wave instruction), while the MFMAs run on the other stage; one
 // barrier per step.
 // ---------------------------------------------------------------------------
-template <int S>
+template <int S, bool DBG>
 __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
                                                 const int32_t* __restrict__ F, int nb, int nao,
                                                 int nao_pad, int kbp, int groups,
-                                                double* __restrict__ Kp) {
+                                                double* __restrict__ Kp,
+                                                int32_t* __restrict__ dbg) {
   constexpr int ROW = 64;             // 64 B rows, 16-byte units swizzled (swz)
   constexpr int NCP = 2 * S * 4;      // 1 KB copies per step (2 panels x S planes x 4)
   constexpr int CPW = (NCP + 7) / 8;  // per wave; waves past the last copy fill spare rows
@@ -510,6 +517,7 @@ __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
   // into from the one being read); rows [panel][a][64], then 16 spare rows
   __shared__ __attribute__((aligned(16))) int8_t L0[2 * S * 64 + 16][ROW];
   __shared__ __attribute__((aligned(16))) int8_t L1[2 * S * 64 + 16][ROW];
+  static_assert(sizeof(L0) + sizeof(L1) <= kLdsLimit, "K stages exceed LDS");
   // group-major logical order, dealt to the XCDs in consecutive ranges: the
   // tiles of one group (which stream the same X_b panels) share an L2
   const int64_t ntile = gridDim.x;
@@ -583,6 +591,20 @@ __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
   auto close_block = [&](int b) {
     const int32_t* Fb = F + (int64_t)b * nao_pad;
     const int fn = Fb[t2 * 64 + wc + r16];
+    if constexpr (DBG) {  // test export: the int32 anti-diagonal sums of block b on this tile
+      const int nu = t2 * 64 + wc + r16;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int mu = t1 * 64 + wr + i * 16 + q * 4 + r;
+          if (mu < nao && nu < nao) {
+#pragma unroll
+            for (int g = 0; g < S; ++g)
+              dbg[(((int64_t)g * nb + b) * nao + mu) * nao + nu] = acc[g][i][r];
+          }
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -692,17 +714,17 @@ template <int S, bool FULLK, int KSUB>
 hipError_t launch_x_sk(hipStream_t st, const double* B, int64_t M, int nao, const int32_t* b_exp,
                        const int8_t* dC, int ncp, int kp, const int32_t* f_col, int nocc,
                        double* X, int xlayout, unsigned long long* xmax, int pblk, const double* D,
-                       double* rowdot, const unsigned long long* cmask) {
+                       double* rowdot, const unsigned long long* cmask, int32_t* dbg) {
   const unsigned gx = (unsigned)((M + 63) / 64);
   if (ncp % 96 == 0) {
     hipLaunchKernelGGL((k_x_int8<S, 6, FULLK, KSUB>), dim3(gx, ncp / 96), dim3(512), 0, st, B, M,
-                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
+                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask, dbg);
   } else if (ncp % 64 == 0) {
     hipLaunchKernelGGL((k_x_int8<S, 4, FULLK, KSUB>), dim3(gx, ncp / 64), dim3(512), 0, st, B, M,
-                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
+                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask, dbg);
   } else {
     hipLaunchKernelGGL((k_x_int8<S, 2, FULLK, KSUB>), dim3(gx, ncp / 32), dim3(512), 0, st, B, M,
-                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
+                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask, dbg);
   }
   return hipGetLastError();
 }
@@ -714,15 +736,15 @@ template <int S>
 hipError_t launch_x_s(hipStream_t st, const double* B, int64_t M, int nao, const int32_t* b_exp,
                       const int8_t* dC, int ncp, int kp, const int32_t* f_col, int nocc,
                       double* X, int xlayout, unsigned long long* xmax, int pblk, const double* D,
-                      double* rowdot, const unsigned long long* cmask, int ksub) {
+                      double* rowdot, const unsigned long long* cmask, int ksub, int32_t* dbg) {
   if (S <= 5 && nao % 128 == 0 && ksub == 2)
     return launch_x_sk<S, true, (S <= 5 ? 2 : 1)>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X,
-                                                   xlayout, xmax, pblk, D, rowdot, cmask);
+                                                   xlayout, xmax, pblk, D, rowdot, cmask, dbg);
   if (nao % 64 == 0)
     return launch_x_sk<S, true, 1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax,
-                                   pblk, D, rowdot, cmask);
+                                   pblk, D, rowdot, cmask, dbg);
   return launch_x_sk<S, false, 1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax,
-                                  pblk, D, rowdot, cmask);
+                                  pblk, D, rowdot, cmask, dbg);
 }
 
 }  // namespace
@@ -731,18 +753,18 @@ hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, i
                          const int32_t* b_exp, const int8_t* dC, int ncp, int kp,
                          const int32_t* f_col, int nocc, double* X, int xlayout,
                          unsigned long long* xmax, int pblk, const double* D, double* rowdot,
-                         const unsigned long long* cmask, int ksub) {
+                         const unsigned long long* cmask, int ksub, int32_t* dbg) {
   const int64_t M = naux * nao;
   if (M <= 0 || nocc <= 0) return hipSuccess;
   switch (s) {
-    case 1: return launch_x_s<1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub);
-    case 2: return launch_x_s<2>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub);
-    case 3: return launch_x_s<3>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub);
-    case 4: return launch_x_s<4>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub);
-    case 5: return launch_x_s<5>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub);
-    case 6: return launch_x_s<6>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub);
-    case 7: return launch_x_s<7>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub);
-    case 8: return launch_x_s<8>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub);
+    case 1: return launch_x_s<1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
+    case 2: return launch_x_s<2>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
+    case 3: return launch_x_s<3>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
+    case 4: return launch_x_s<4>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
+    case 5: return launch_x_s<5>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
+    case 6: return launch_x_s<6>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
+    case 7: return launch_x_s<7>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
+    case 8: return launch_x_s<8>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
     default: return hipErrorInvalidValue;
   }
 }
@@ -780,7 +802,7 @@ int k_int8_resident(int s) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
 #define DFJK_KOCC(SS) \
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_k_int8<SS>), 512, 0)
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_k_int8<SS, false>), 512, 0)
   switch (s) {
     case 1: DFJK_KOCC(1); break;
     case 2: DFJK_KOCC(2); break;
@@ -799,11 +821,16 @@ int k_int8_resident(int s) {
 }
 
 hipError_t launch_k_int8(hipStream_t st, int s, const int8_t* Xd, const int32_t* F, int nb,
-                         int nao, int nao_pad, int kbp, int groups, double* Kp) {
+                         int nao, int nao_pad, int kbp, int groups, double* Kp, int32_t* dbg) {
   const int nt = nao_pad / 64;
   const dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)groups);
 #define DFJK_K(SS) \
-  hipLaunchKernelGGL((k_k_int8<SS>), grid, dim3(512), 0, st, Xd, F, nb, nao, nao_pad, kbp, groups, Kp)
+  if (dbg)                                                                                     \
+    hipLaunchKernelGGL((k_k_int8<SS, true>), grid, dim3(512), 0, st, Xd, F, nb, nao, nao_pad, kbp, \
+                       groups, Kp, dbg);                                                        \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_k_int8<SS, false>), grid, dim3(512), 0, st, Xd, F, nb, nao, nao_pad,  \
+                       kbp, groups, Kp, nullptr)
   switch (s) {
     case 1: DFJK_K(1); break;
     case 2: DFJK_K(2); break;

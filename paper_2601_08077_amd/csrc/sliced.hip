@@ -86,6 +86,7 @@ __global__ __launch_bounds__(256 * NH) void k_x_dig(
   constexpr int PF = S == 4 ? 2 : 1;
   constexpr bool DPF = S >= 4 && S <= 6;  // D fragments prefetched too
   __shared__ __attribute__((aligned(16))) int8_t Cs[NBUF][S][NT][ROW];
+  static_assert(sizeof(Cs) <= kLdsLimit, "C stages exceed LDS");
   const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
   const int wr = w & 3, half = w >> 2;
   int64_t m0 = (int64_t)blockIdx.x * 64;

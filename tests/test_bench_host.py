@@ -20,11 +20,14 @@ def _load(path):
 def test_stage_units_of_the_bench_configuration():
     b = _load(os.path.join(ROOT, "bench.py"))
     nao, naux, nocc = 768, 3072, 96
-    # X at s = 7: 28 digit pairs, each 2 naux nao^2 nocc int8 ops; B read once
-    # (8 B per element) and X written once
+    # X at s = 7: 28 digit pairs, each 2 naux nao^2 nocc int8 ops; the stored
+    # (lower-triangle) B read once plus C, X a streamed workspace
     ops, byts = b.stage_units("x", 7, nao, naux, nocc)
     assert ops == 28 * 2 * naux * nao * nao * nocc == 9_740_985_827_328
-    assert byts == 8 * naux * nao * nao + 8 * naux * nao * nocc == 16_307_453_952
+    assert byts == 8 * naux * nao * (nao + 1) // 2 + 8 * nao * nocc == 7_257_784_320
+    # the digits of X: X read once, 7 planes written once
+    _, byts = b.stage_units("slice_x", 7, nao, naux, nocc)
+    assert byts == 15 * naux * nao * nocc
     # K at s = 7: the symmetric products over nao (nao + 1) / 2 pairs, x2 ops per MAC
     ops, byts = b.stage_units("k", 7, nao, naux, nocc)
     assert ops == 28 * nao * (nao + 1) * naux * nocc == 4_876_834_701_312
@@ -38,12 +41,22 @@ def test_stage_units_of_the_bench_configuration():
 
 def test_roofline_picks_the_binding_roof():
     b = _load(os.path.join(ROOT, "bench.py"))
+    # X at s = 7: 9.74e12 int8 ops take 1.95 ms at 5 POPS, its 7.26 GB 0.91 ms
+    # at 8 TB/s: the matrix cores bind
     r = b.roofline_of("x", 6.0, 7, 768, 3072, 96)
-    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
-    assert abs(r["achieved"] - 16_307_453_952 / 6e-3 / 1e9) < 1e-6
-    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-12
-    r = b.roofline_of("k", 2.0, 7, 768, 3072, 96)
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 5000.0
+    assert abs(r["achieved"] - 9_740_985_827_328 / 6e-3 / 1e12) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / 5000.0) < 1e-12
+    # at s = 1 the bytes bind
+    r = b.roofline_of("x", 2.0, 1, 768, 3072, 96)
+    assert r["bound"] == "hbm" and r["peak"] == 8000.0
+    r = b.roofline_of("k", 2.0, 7, 768, 3072, 96, {"int8": 4000.0})
     assert r["bound"] == "mfma" and r["peak"] == 5000.0
+    assert abs(r["frac_of_measured_peak"] - r["achieved"] / 4000.0) < 1e-12
+    # J and the slicing of X are byte-bound; the FP64 X product is flop-bound
+    assert b.roofline_of("j", 1.0, 7, 768, 3072, 96)["bound"] == "hbm"
+    assert b.roofline_of("slice_x", 1.0, 7, 768, 3072, 96)["bound"] == "hbm"
+    assert b.roofline_of("x", 9.0, 0, 768, 3072, 96)["bound"] == "mfma"
 
 
 def test_traffic_record_used_only_while_sources_unchanged(tmp_path):

@@ -98,6 +98,39 @@ def test_mlp_train_steps_track_oracle(torch_dev, ctx):
             assert np.abs(got[k] - p[k]).max() <= 2e-4 * (1 + np.abs(p[k]).max()), (step, k)
 
 
+@pytest.mark.parametrize("seed,n,frac", [(11, 96, 0.6), (12, 257, 0.15)])
+def test_mlp_gradient_matches_oracle(torch_dev, ctx, seed, n, frac):
+    """The backward pass itself: after one Adam step from zero moments the
+    first moment is (1 - beta1) g = 0.1 g and the second (1 - beta2) g^2 =
+    0.001 g^2, element by element, with g the oracle's analytic gradient of
+    the masked loss (a gradient off by any factor fails here, although Adam's
+    update would hide it)."""
+    torch = torch_dev
+    rng = np.random.default_rng(seed)
+    N = n + 40
+    p = _params(seed)
+    x = rng.standard_normal((N, 16)).astype(np.float32)
+    t = rng.standard_normal((N, 8)).astype(np.float32)
+    m = (rng.random((N, 8)) < frac).astype(np.float32)
+    idx = rng.permutation(N)[:n].astype(np.int32)
+    prm = _dev(torch, _pack(p))
+    m1 = torch.zeros_like(prm)
+    m2 = torch.zeros_like(prm)
+    ctx.df_mlp_train_step(prm, m1, m2, 1, _dev(torch, x), _dev(torch, t), _dev(torch, m),
+                          _dev(torch, idx), n, 1e-3, None)
+    torch.cuda.synchronize()
+    _, g = octl.loss_and_grads(p, x[idx].astype(np.float64), t[idx].astype(np.float64),
+                               m[idx].astype(np.float64))
+    got1 = _unpack(m1.cpu().numpy())
+    got2 = _unpack(m2.cpu().numpy())
+    for k in octl.ORDER:
+        gk = g[k]
+        scale = np.abs(gk).max()
+        assert scale > 0, k
+        assert np.abs(got1[k] / 0.1 - gk).max() <= 1e-5 * scale, k
+        assert np.abs(got2[k] / 0.001 - gk * gk).max() <= 2e-5 * scale * scale, k
+
+
 def test_choose_slices_matches_oracle(torch_dev, ctx):
     torch = torch_dev
     rng = np.random.default_rng(3)

@@ -121,3 +121,78 @@ def _check_j(full, got):
     jb = (2.02 * naux * U * (np.abs(rho) @ absB) + drho @ absB).reshape(Js.shape)
     assert np.all(np.abs(got["Js"] - Js) <= jb)
     assert got["e"][0] == pytest.approx(0.5 * rho @ rho, rel=1e-12)
+
+
+def test_fullsize_sliced_mode_sampled(full):
+    """The sliced build (B held as digit planes, rho and J from digits) at the
+    full size: K restricted to the sample is bit-exact against the oracle (the
+    sliced K equals the plain emulated K), J within its stated bound of the
+    FP64 J, and a prefix of the planes serves every lower level."""
+    import torch
+    from paper_2601_08077_amd.binding import df_prepare_b_size
+    p, ctx = full["p"], full["ctx"]
+    B = p["B"]
+    naux, nao, _ = B.shape
+    C = p["C_host"]
+    planes = 7
+    dig = torch.empty(df_prepare_b_size(naux, nao, planes), dtype=torch.int8, device="cuda")
+    be = torch.empty(naux * nao, dtype=torch.int32, device="cuda")
+    ctx.df_prepare_b(B, planes, be, dig)
+    J = torch.empty((nao, nao), dtype=torch.float64, device="cuda")
+    K = torch.empty_like(J)
+    en = torch.empty(2, dtype=torch.float64, device="cuda")
+    eb = torch.empty(2, dtype=torch.float64, device="cuda")
+    St = full["St"]
+    try:
+        for s in (3, 5, 7):
+            ctx.df_set_precision(s)
+            ctx.df_set_pblk(64)
+            ctx.df_set_k_groups(0)
+            ctx.df_build_jk_sliced(dig, planes, be, naux, nao, p["C"], p["occ"], p["D"], J, K,
+                                   en, eb)
+            torch.cuda.synchronize()
+            assert ctx.df_get_status() == 0
+            Kss = K.index_select(0, St).index_select(1, St).cpu().numpy()
+            Js = J.index_select(0, St).cpu().numpy()
+            bound = eb.cpu().numpy()
+            X, _, _ = em.emulated_x(full["Bsub"], C, s)
+            Kref, _ = em.emulated_k(X, s, occ=p["occ"], pblk=64, groups=ctx.df_get_k_groups())
+            assert np.array_equal(Kss, Kref)
+            Jfp = np.einsum("p,pmn->mn", full["rho"], full["Bsub"])
+            assert np.abs(Js - Jfp).max() <= bound[1]
+    finally:
+        del dig
+
+
+def test_fullsize_mixed_block_counts_sampled(full):
+    """Per-aux-block slice counts (all 48 blocks at their own s in 2..8) at the
+    full size: K restricted to the sample bit-exact against the oracle's
+    per-block build, and within the stated bound of the FP64 K."""
+    import torch
+    p, ctx = full["p"], full["ctx"]
+    B = p["B"]
+    naux, nao, _ = B.shape
+    nocc = p["C"].shape[1]
+    C = p["C_host"]
+    nb = naux // 64
+    sb = [2 + (3 * b) % 7 for b in range(nb)]
+    assert sorted(set(sb)) == list(range(2, 9))
+    J = torch.empty((nao, nao), dtype=torch.float64, device="cuda")
+    K = torch.empty_like(J)
+    en = torch.empty(2, dtype=torch.float64, device="cuda")
+    eb = torch.empty(1, dtype=torch.float64, device="cuda")
+    ctx.df_set_pblk(64)
+    try:
+        ctx.df_set_block_precision(sb)
+        ctx.ensure_workspace(naux, nao, nocc)
+        ctx.df_build_jk(B, full["be"], p["C"], p["occ"], p["D"], J, K, en, eb)
+        torch.cuda.synchronize()
+        assert ctx.df_get_status() == 0
+    finally:
+        ctx.df_set_block_precision(None)
+    St = full["St"]
+    Kss = K.index_select(0, St).index_select(1, St).cpu().numpy()
+    _, Kref, _ = em.emulated_xk_blocks(full["Bsub"], C, sb, occ=p["occ"], pblk=64)
+    assert np.array_equal(Kss, Kref)
+    Kfp = jk.k_rows_fp64(full["Bsub"], C, occ=p["occ"])
+    assert np.abs(Kss - Kfp).max() <= float(eb.cpu()[0])

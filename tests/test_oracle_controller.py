@@ -133,6 +133,28 @@ def test_features_shape_and_bias():
     assert f[-1] == 1.0 and f[3] == 0.2 and f[9] == pytest.approx(-8.0)
 
 
+def test_features_every_entry_by_hand():
+    """All 16 features on a block whose statistics are known in closed form."""
+    Bb = np.zeros((2, 3, 3))
+    Bb[0, 0, 0] = 3.0
+    Bb[1, 2, 1] = -4.0            # max |B_b| = 4, ||B_b||_F = 5
+    Xp = np.zeros((2, 3, 2))
+    Xp[1, 0, 1] = -0.5            # max |X_b| = 0.5, ||X_b||_F = 0.5
+    Xp[0, 2, 0] = 0.0
+    C = np.array([[0.25, -0.125], [0.0, 0.0625], [-0.25, 0.0]])   # max |C| = 0.25
+    f = ctl.block_features(Bb, Xp, C, 1e-3, 3, 12, 1e-7, 8.0, 1e-10, 64, 256, 8, 5, 2, 8)
+    want = [2.0, np.log2(5.0), -3.0, 0.25, -7.0, -2.0, -1.0, -1.0, 3.0, -10.0, 6.0, 8.0,
+            3.0, 5 / 8, 0.25, 1.0]
+    assert f.shape == (16,)
+    assert np.allclose(f, want, rtol=0, atol=1e-12)
+    # zero statistics take the stated floors (log2 -> -1100, log10 -> -330)
+    z = ctl.block_features(np.zeros((1, 2, 2)), np.zeros((1, 2, 1)), np.zeros((2, 1)), 0.0, 0,
+                           5, 0.0, 0.0, 1e-6, 2, 8, 1, 0, 0, 1)
+    assert list(z[[0, 1, 2, 4, 5, 6, 7, 8]]) == [-1100.0, -1100.0, -330.0, -330.0, -1100.0,
+                                                 -1100.0, -1100.0, -1100.0]
+    assert list(z[[3, 9, 10, 11, 12, 13, 14, 15]]) == [0.0, -6.0, 1.0, 3.0, 0.0, 0.0, 0.0, 1.0]
+
+
 def _slopes(nb, seed=0):
     rng = np.random.default_rng(seed)
     a = rng.uniform(-12, 0, nb)                 # block scale (log10 err at s = 0)
