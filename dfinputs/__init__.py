@@ -187,3 +187,64 @@ def spot_blocks(nb, count, iteration, seed=0):
     """Blocks checked in FP64 at one iteration: `count` distinct draws."""
     rng = np.random.default_rng([seed, iteration])
     return [int(b) for b in rng.choice(nb, size=min(count, nb), replace=False)]
+
+
+def pack_lower(B):
+    """The packed storage of a symmetric three-index tensor: B [naux][nao][nao]
+    (NumPy or torch) -> [naux][nao (nao + 1) / 2], the lower triangle of each
+    B_P by rows (element (mu, nu), mu >= nu, at mu (mu + 1) / 2 + nu)."""
+    nao = B.shape[1]
+    i, j = np.tril_indices(nao)
+    if isinstance(B, np.ndarray):
+        return np.ascontiguousarray(B[:, i, j])
+    import torch
+    ti = torch.from_numpy(i).to(B.device)
+    tj = torch.from_numpy(j).to(B.device)
+    out = torch.empty((B.shape[0], i.size), dtype=B.dtype, device=B.device)
+    for p0 in range(0, B.shape[0], 256):   # chunks keep the index temporaries small
+        out[p0:p0 + 256] = B[p0:p0 + 256][:, ti, tj]
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Synthetic SCF problem (a one-electron part with a gap and a weakened
+# two-electron tensor, so that plain Roothaan iterations converge)
+# ----------------------------------------------------------------------------
+def scf_two_electron_scale(nao):
+    """Factor applied to B in the synthetic SCF: 0.05 (64 / nao)^(3/4), which
+    keeps the two-electron part a perturbation of h's gap at every size, so the
+    Roothaan iterations contract by about 10-20x per iteration (measured for
+    nao 64 .. 256 with naux = 4 nao, nocc = nao / 8, L = nao / 8)."""
+    return 0.05 * (64.0 / nao) ** 0.75
+
+
+def scf_hcore(nao, nocc, seed=0):
+    """Synthetic one-electron matrix h = Q diag(lam) Q^T: Q orthogonal (QR of an
+    N(0, 1) matrix from default_rng(seed + 7)), occupied levels
+    lam_i = -1 - 0.5 i / nocc (i < nocc), virtual levels
+    lam_i = 0.5 + 1.5 (i - nocc) / (nao - nocc): a gap of 1.5 at the Fermi level."""
+    rng = np.random.default_rng(seed + 7)
+    Q, _ = np.linalg.qr(rng.standard_normal((nao, nao)))
+    lam = np.concatenate([-1.0 - 0.5 * np.arange(nocc) / nocc,
+                          0.5 + 1.5 * np.arange(nao - nocc) / max(nao - nocc, 1)])
+    return np.ascontiguousarray((Q * lam) @ Q.T), lam
+
+
+def make_scf_problem(nao, naux, nocc, seed=0, L=None):
+    """Host SCF problem: dict(B (scaled), h, lam) with B from make_problem
+    (L = nao / 8 unless given, no per-row scale) times scf_two_electron_scale."""
+    L = max(nao / 8.0, 1.0) if L is None else L
+    p = make_problem(nao=nao, naux=naux, nocc=nocc, L=L, seed=seed)
+    h, lam = scf_hcore(nao, nocc, seed)
+    return dict(B=p["B"] * scf_two_electron_scale(nao), h=h, lam=lam, nocc=nocc)
+
+
+def make_scf_problem_device(nao, naux, nocc, seed=0, L=None):
+    """As make_scf_problem with B drawn on the GPU (make_problem_device)."""
+    import torch
+    L = max(nao / 8.0, 1.0) if L is None else L
+    p = make_problem_device(nao=nao, naux=naux, nocc=nocc, L=L, seed=seed)
+    B = p["B"]
+    B.mul_(scf_two_electron_scale(nao))
+    h, lam = scf_hcore(nao, nocc, seed)
+    return dict(B=B, h=torch.from_numpy(h).to(B.device), h_host=h, lam=lam, nocc=nocc)
