@@ -16,8 +16,12 @@ from the arithmetic:
   A level-s slicing keeps d_1..d_s (a prefix of the level-8 digits).
 * Products: P_ab = sum_k dA_a dB_b for a + b <= s + 1 (s(s+1)/2 pairs); the
   pairs of one anti-diagonal g = a + b are summed exactly: S_g (an integer).
-* Recombination: Z = sum over g from s+1 down to 2 of ldexp(S_g, e_r + f_c +
-  4 - 8 g), in FP64 with round-to-nearest-even, smallest weight first.
+  An alternative scheme keeps ``extra`` more anti-diagonals, a + b <= s + 1 +
+  extra (a, b <= s; extra = s - 1 keeps all s^2 pairs): more products for a
+  smaller dropped-pair error at the same slice count (the outlook of Sec. 5
+  on choosing slice counts; Sec. 2.3).
+* Recombination: Z = sum over g from s+1+extra down to 2 of ldexp(S_g, e_r +
+  f_c + 4 - 8 g), in FP64 with round-to-nearest-even, smallest weight first.
 * The K pipeline (Eqs. df-k-blk-1/2): X_b = emu(B_b, C) for each block of
   ``pblk`` consecutive aux indices, X_b sliced per row mu over (P in b, i),
   K_b = emu(X_b X_b^T), K = occ * sum_b K_b with b ascending (optionally
@@ -97,9 +101,12 @@ def digit_weight_exp(e, k):
 # ----------------------------------------------------------------------------
 # Exact integer slice products
 # ----------------------------------------------------------------------------
-def pairs(s):
-    """The (a, b) slice pairs kept at level s: a + b <= s + 1 (1-based)."""
-    return [(a, b) for a in range(1, s + 1) for b in range(1, s + 2 - a)]
+def pairs(s, extra=0):
+    """The (a, b) slice pairs kept at level s: a + b <= s + 1 + extra, a, b <= s
+    (1-based); extra = 0 is the triangle of s(s+1)/2 pairs."""
+    if not 0 <= extra <= max(s - 1, 0):
+        raise ValueError("extra must be in 0..s-1")
+    return [(a, b) for a in range(1, s + 1) for b in range(1, s + 1) if a + b <= s + 1 + extra]
 
 
 def int32_guard_ok(k, s):
@@ -107,7 +114,7 @@ def int32_guard_ok(k, s):
     return s * k * 16384 < 2 ** 31
 
 
-def slice_pair_products(dA, dB, s):
+def slice_pair_products(dA, dB, s, extra=0):
     """P_ab = dA_a @ dB_b for every kept pair, as exact int64 arrays.
 
     Uses FP64 matmul on integer-valued arrays: every partial sum is an integer
@@ -118,33 +125,33 @@ def slice_pair_products(dA, dB, s):
     if k * 16384 >= 2 ** 53:
         raise OverflowError("inner dimension too large for exact FP64 integer sums")
     out = {}
-    for a, b in pairs(s):
+    for a, b in pairs(s, extra):
         pa = dA[a - 1].astype(np.float64)
         pb = dB[b - 1].astype(np.float64)
         out[(a, b)] = np.rint(pa @ pb).astype(np.int64)
     return out
 
 
-def diagonal_sums(pair_products, s):
-    """S_g = sum_{a+b=g} P_ab for g = 2..s+1; returned as S[g - 2]."""
+def diagonal_sums(pair_products, s, extra=0):
+    """S_g = sum_{a+b=g} P_ab for g = 2..s+1+extra; returned as S[g - 2]."""
     first = next(iter(pair_products.values()))
-    S = np.zeros((s,) + first.shape, dtype=np.int64)
+    S = np.zeros((s + extra,) + first.shape, dtype=np.int64)
     for (a, b), p in pair_products.items():
         S[a + b - 2] += p
     return S
 
 
-def slice_products(dA, dB, s):
+def slice_products(dA, dB, s, extra=0):
     """Anti-diagonal integer sums S[g - 2] of the level-s slice products."""
-    return diagonal_sums(slice_pair_products(dA, dB, s), s)
+    return diagonal_sums(slice_pair_products(dA, dB, s, extra), s, extra)
 
 
-def slice_products_loops(dA, dB, s):
+def slice_products_loops(dA, dB, s, extra=0):
     """Same as ``slice_products`` with pure Python integer loops (tiny inputs)."""
     _, r, k = dA.shape
     c = dB.shape[2]
-    S = [[[0] * c for _ in range(r)] for _ in range(s)]
-    for a, b in pairs(s):
+    S = [[[0] * c for _ in range(r)] for _ in range(s + extra)]
+    for a, b in pairs(s, extra):
         for i in range(r):
             for j in range(c):
                 S[a + b - 2][i][j] += sum(int(dA[a - 1][i][t]) * int(dB[b - 1][t][j])
@@ -155,23 +162,23 @@ def slice_products_loops(dA, dB, s):
 # ----------------------------------------------------------------------------
 # Recombination and emulated products
 # ----------------------------------------------------------------------------
-def recombine(S, e_rows, f_cols, s):
-    """Z = sum_{g = s+1 .. 2} ldexp(S_g, e_r + f_c + 4 - 8g), smallest weight first."""
+def recombine(S, e_rows, f_cols, s, extra=0):
+    """Z = sum_{g = s+1+extra .. 2} ldexp(S_g, e_r + f_c + 4 - 8g), smallest weight first."""
     e_rows = np.asarray(e_rows, dtype=np.int64)
     f_cols = np.asarray(f_cols, dtype=np.int64)
     base = e_rows[:, None] + f_cols[None, :] + 4
     Z = np.zeros(S.shape[1:], dtype=np.float64)
-    for g in range(s + 1, 1, -1):
+    for g in range(s + 1 + extra, 1, -1):
         term = np.ldexp(S[g - 2].astype(np.float64), (base - 8 * g).astype(np.int32))
         Z = Z + term
     return Z
 
 
-def emulated_matmul(A, Bm, s):
+def emulated_matmul(A, Bm, s, extra=0):
     """A @ Bm emulated at level s (rows of A and columns of Bm sliced over k)."""
     dA, e = slice_rows(A, s)
     dB, f = slice_cols(Bm, s)
-    return recombine(slice_products(dA, dB, s), e, f, s)
+    return recombine(slice_products(dA, dB, s, extra), e, f, s, extra)
 
 
 # ----------------------------------------------------------------------------
@@ -183,35 +190,37 @@ def eps_slice(s):
     return tail + 2.0 ** -FIX_BITS
 
 
-def kappa(s, k=None):
+def kappa(s, k=None, extra=0):
     """Per-element bound factor: |Z - Z_hat| <= k * 2^(e_r + f_c) * kappa(s).
 
     s >= 1: 2 eps + eps^2 (slicing of both operands) + the pairs with
-    a + b >= s + 2 that are dropped (each |d_a d_b| <= 2^14 at weight
-    2^(e + f + 4 - 8g), 2s + 1 - g of them per g) + the s - 1 roundings of the
-    recombination, each bounded by u times the sum of |terms| <= 1.016 k 2^(e+f).
+    a + b >= s + 2 + extra that are dropped (each |d_a d_b| <= 2^14 at weight
+    2^(e + f + 4 - 8g), 2s + 1 - g of them per g) + the s + extra - 1 roundings
+    of the recombination, each bounded by u times the sum of |terms| <=
+    1.016 k 2^(e+f).
     s == 0 (plain FP64 dot products of length k): gamma_k = k u / (1 - k u).
     """
     if s == 0:
         ku = k * UNIT_ROUNDOFF
         return ku / (1.0 - ku)
     eps = eps_slice(s)
-    dropped = sum((2 * s + 1 - g) * 2.0 ** (18 - 8 * g) for g in range(s + 2, 2 * s + 1))
-    rounding = (s - 1) * UNIT_ROUNDOFF * 1.016 * (1 + UNIT_ROUNDOFF) ** s
+    dropped = sum((2 * s + 1 - g) * 2.0 ** (18 - 8 * g) for g in range(s + 2 + extra, 2 * s + 1))
+    nadd = s + extra - 1
+    rounding = nadd * UNIT_ROUNDOFF * 1.016 * (1 + UNIT_ROUNDOFF) ** (nadd + 1)
     return 2 * eps + eps * eps + dropped + rounding
 
 
-def matmul_error_bound(e_rows, f_cols, k, s):
+def matmul_error_bound(e_rows, f_cols, k, s, extra=0):
     """Elementwise bound k * 2^(e_r + f_c) * kappa for one product."""
     e_rows = np.asarray(e_rows, dtype=np.float64)
     f_cols = np.asarray(f_cols, dtype=np.float64)
-    return k * np.exp2(e_rows[:, None] + f_cols[None, :]) * kappa(s, k)
+    return k * np.exp2(e_rows[:, None] + f_cols[None, :]) * kappa(s, k, extra)
 
 
 # ----------------------------------------------------------------------------
 # The emulated K pipeline of Eqs. (df-k-blk-1) / (df-k-blk-2)
 # ----------------------------------------------------------------------------
-def emulated_x(B, C, s):
+def emulated_x(B, C, s, extra=0):
     """Eq. (5) emulated: X[P] = emu(B[P] rows (P, mu) over nu, C columns i over nu).
 
     Returns (X, e_B[naux, nao], f_C[nocc]).  For s == 0 this is the FP64 product.
@@ -227,7 +236,7 @@ def emulated_x(B, C, s):
         return np.matmul(B, C), e_B, f_C
     dB, _ = slice_rows(rows, s)
     dC, _ = slice_cols(C, s)
-    Z = recombine(slice_products(dB, dC, s), e_B.reshape(-1), f_C, s)
+    Z = recombine(slice_products(dB, dC, s, extra), e_B.reshape(-1), f_C, s, extra)
     return Z.reshape(naux, nrow, nocc), e_B, f_C
 
 
@@ -248,7 +257,7 @@ def block_groups(nb, groups):
     return [(g * nb // groups, (g + 1) * nb // groups) for g in range(groups)]
 
 
-def emulated_k(X, s, occ=2.0, pblk=64, groups=1):
+def emulated_k(X, s, occ=2.0, pblk=64, groups=1, extra=0):
     """Eq. (6) blocked and emulated: K = occ * sum_b emu(X_b X_b^T).
 
     The block partial sums are added in ascending order inside ``groups``
@@ -273,14 +282,14 @@ def emulated_k(X, s, occ=2.0, pblk=64, groups=1):
                 Kb = Xb @ Xb.T
             else:
                 dX, _ = slice_rows(Xb, s)
-                S = slice_products(dX, dX.transpose(0, 2, 1), s)
-                Kb = recombine(S, F[bi], F[bi], s)
+                S = slice_products(dX, dX.transpose(0, 2, 1), s, extra)
+                Kb = recombine(S, F[bi], F[bi], s, extra)
             Kg = Kg + Kb
         Kacc = Kacc + Kg
     return occ * Kacc, F
 
 
-def k_error_bound(e_B, f_C, F, s, occ=2.0, pblk=64, nocc=None):
+def k_error_bound(e_B, f_C, F, s, occ=2.0, pblk=64, nocc=None, extra=0):
     """Elementwise bound on |K_hat - K| for the emulated pipeline: s one slice
     count (>= 1) or one per block (0 = an FP64 block: gamma factors).
 
@@ -304,13 +313,13 @@ def k_error_bound(e_B, f_C, F, s, occ=2.0, pblk=64, nocc=None):
     kabs = np.zeros((nao, nao))
     for bi, (p0, p1) in enumerate(blocks):
         kb = (p1 - p0) * nocc
-        kap1 = kappa(s_of(bi), nao)
+        kap1 = kappa(s_of(bi), nao, extra if s_of(bi) else 0)
         eb = np.exp2(e_B[p0:p1])                       # (|b|, nao)
         A = nao * kap1 * Fsum * np.sum(eb, axis=0)     # (nao,)
         dmax = nao * kap1 * Fmax * np.max(eb, axis=0)  # (nao,)
         pf = np.exp2(np.asarray(F[bi], dtype=np.float64))
         prop = A[:, None] * pf[None, :] + (pf[:, None] + dmax[:, None]) * A[None, :]
-        kap2 = kappa(s_of(bi), kb)
+        kap2 = kappa(s_of(bi), kb, extra if s_of(bi) else 0)
         emu2 = kb * np.outer(pf, pf) * kap2
         bound += prop + emu2
         kabs += kb * np.outer(pf, pf) * (1.0 + kap2)
@@ -323,7 +332,7 @@ def k_error_bound(e_B, f_C, F, s, occ=2.0, pblk=64, nocc=None):
     return bound
 
 
-def emulated_build_jk(B, C, s, occ=2.0, D=None, pblk=64, groups=1):
+def emulated_build_jk(B, C, s, occ=2.0, D=None, pblk=64, groups=1, extra=0):
     """The emulated build: rho and J in FP64 (Eqs. 3-4), X and K emulated.
 
     Returns dict(rho, J, X, K, e_j, e_x, D, e_B, f_C, F, bound) where
@@ -336,10 +345,10 @@ def emulated_build_jk(B, C, s, occ=2.0, D=None, pblk=64, groups=1):
         D = occ * (C @ C.T)
     rho = _jk.rho_of(B, D)
     J = _jk.j_of(B, rho)
-    X, e_B, f_C = emulated_x(B, C, s)
-    K, F = emulated_k(X, s, occ=occ, pblk=pblk, groups=groups)
+    X, e_B, f_C = emulated_x(B, C, s, extra)
+    K, F = emulated_k(X, s, occ=occ, pblk=pblk, groups=groups, extra=extra)
     e_j, e_x = _jk.energies(rho, D, K)
-    bound = k_error_bound(e_B, f_C, F, s, occ=occ, pblk=pblk) if s else None
+    bound = k_error_bound(e_B, f_C, F, s, occ=occ, pblk=pblk, extra=extra) if s else None
     return dict(rho=rho, J=J, X=X, K=K, e_j=e_j, e_x=e_x, D=D,
                 e_B=e_B, f_C=f_C, F=F, bound=bound)
 

@@ -323,3 +323,93 @@ def test_block_slice_count_only_moves_its_block():
     assert not np.array_equal(lo["X"][16:32], hi["X"][16:32])
     K64 = jk.build_jk(p["B"], p["C"], D=p["D"])["K"]
     assert np.abs(hi["K"] - K64).max() < np.abs(lo["K"] - K64).max()
+
+
+# ---------------------------------------------------------------------------- extra pairs
+def test_extra_pair_counts():
+    for s in range(1, 9):
+        assert len(em.pairs(s, 0)) == s * (s + 1) // 2
+        if s > 1:
+            assert len(em.pairs(s, 1)) == s * (s + 1) // 2 + s - 1   # the diagonal g = s + 2
+        assert len(em.pairs(s, s - 1)) == s * s                      # every pair
+    with pytest.raises(ValueError):
+        em.pairs(3, 3)
+
+
+def test_two_digit_inputs_exact_with_one_extra_diagonal_at_s2():
+    # the inputs of test_two_digit_inputs_need_three_slices: at s = 2 the (2, 2)
+    # pair sits on g = 4 = s + 2, so one extra anti-diagonal makes them exact
+    rng = np.random.default_rng(6)
+    xa = rng.integers(-63, 64, size=(5, 40))
+    xa[:, 0] = 50
+    ya = rng.integers(-128, 128, size=(5, 40))
+    xb = rng.integers(-63, 64, size=(40, 4))
+    xb[0, :] = 45
+    yb = rng.integers(-128, 128, size=(40, 4))
+    A = (256 * xa + ya).astype(np.float64)
+    Bm = (256 * xb + yb).astype(np.float64)
+    exact = ((256 * xa + ya) @ (256 * xb + yb)).astype(np.float64)
+    assert np.array_equal(em.emulated_matmul(A, Bm, 2, extra=1), exact)
+    assert not np.array_equal(em.emulated_matmul(A, Bm, 2, extra=0), exact)
+
+
+@pytest.mark.parametrize("s,extra", [(2, 1), (4, 1), (5, 2), (7, 1)])
+def test_extra_products_equal_python_loops(s, extra):
+    rng = np.random.default_rng(50 + s)
+    A = _wide(rng, (3, 9))
+    Bm = _wide(rng, (9, 4))
+    dA, _ = em.slice_rows(A, s)
+    dB, _ = em.slice_cols(Bm, s)
+    S = em.slice_products(dA, dB, s, extra)
+    assert S.shape[0] == s + extra
+    assert np.array_equal(S, em.slice_products_loops(dA, dB, s, extra))
+    # the first s anti-diagonals are those of the plain scheme
+    assert np.array_equal(S[:s], em.slice_products(dA, dB, s))
+
+
+@pytest.mark.parametrize("s", range(2, 9))
+def test_extra_diagonal_within_bound_exact_rational(s):
+    rng = np.random.default_rng(70 + s)
+    A = _wide(rng, (3, 24), decades=4)
+    Bm = _wide(rng, (24, 3), decades=4)
+    Z = em.emulated_matmul(A, Bm, s, extra=1)
+    _, e = em.slice_rows(A, s)
+    _, f = em.slice_cols(Bm, s)
+    bound = em.matmul_error_bound(e, f, A.shape[1], s, extra=1)
+    if s <= 7:  # at s = 8 the rounding of one more addition outweighs what it drops
+        assert em.kappa(s, 24, 1) < em.kappa(s, 24, 0)
+    for r in range(3):
+        for c in range(3):
+            exact = sum(Fraction(float(A[r, k])) * Fraction(float(Bm[k, c])) for k in range(24))
+            assert abs(Fraction(float(Z[r, c])) - exact) <= Fraction(float(bound[r, c]))
+
+
+def test_full_pairs_equal_product_of_sliced_operands():
+    # all s^2 pairs: the result is the exact product of the level-s slices,
+    # up to the 2s - 2 FP64 roundings of the recombination
+    rng = np.random.default_rng(90)
+    s = 3
+    A = _wide(rng, (4, 16), decades=3)
+    Bm = _wide(rng, (16, 5), decades=3)
+    dA, e = em.slice_rows(A, s)
+    dB, f = em.slice_cols(Bm, s)
+    Z = em.emulated_matmul(A, Bm, s, extra=s - 1)
+    for r in range(4):
+        for c in range(5):
+            a_hat = [sum(Fraction(int(dA[j, r, k])) * Fraction(2) ** int(e[r] + 2 - 8 * (j + 1))
+                         for j in range(s)) for k in range(16)]
+            b_hat = [sum(Fraction(int(dB[j, k, c])) * Fraction(2) ** int(f[c] + 2 - 8 * (j + 1))
+                         for j in range(s)) for k in range(16)]
+            exact = sum(x * y for x, y in zip(a_hat, b_hat))
+            tol = Fraction(2 * s * 2 ** -53) * sum(abs(x * y) for x, y in zip(a_hat, b_hat))
+            assert abs(Fraction(float(Z[r, c])) - exact) <= tol + Fraction(2) ** -1074
+
+
+def test_extra_k_pipeline_within_bound(prob):
+    for s in (3, 5):
+        ref = em.emulated_build_jk(prob["B"], prob["C"], s, D=prob["D"], pblk=16, extra=1)
+        plain = em.emulated_build_jk(prob["B"], prob["C"], s, D=prob["D"], pblk=16)
+        fp = jk.build_jk(prob["B"], prob["C"], D=prob["D"])
+        assert np.all(np.abs(ref["K"] - fp["K"]) <= ref["bound"])
+        assert np.all(ref["bound"] <= plain["bound"])
+        assert np.array_equal(ref["K"], ref["K"].T)
