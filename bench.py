@@ -228,6 +228,71 @@ def adaptive_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def scf_workload(args):
+    """Synthetic SCF (Fock = h + J - K/2, diagonalise; Sec. 4.3): the adaptive
+    rule vs all-FP64 and a fixed level-4 run, nao 1024, naux 4096, nocc 128."""
+    import numpy as np
+    import torch
+    import dfinputs
+    from paper_2601_08077_amd import DF_PACKED, Context, adaptive, scf
+
+    nao, naux, nocc, n_iter = args.scf_nao, 4 * args.scf_nao, args.scf_nao // 8, args.scf_iters
+    log(f"scf: nao {nao} naux {naux} nocc {nocc}, {n_iter} iterations")
+    p = dfinputs.make_scf_problem_device(nao=nao, naux=naux, nocc=nocc, seed=0)
+    B = dfinputs.pack_lower(p["B"])
+    del p["B"]
+    torch.cuda.empty_cache()
+    ctx = Context()
+    ctx.df_set_pblk(64)
+    ctx.ensure_workspace(naux, nao, nocc)
+    be = torch.empty(naux * nao, dtype=torch.int32, device="cuda")
+    ctx.df_b_exponents(B, be, layout=DF_PACKED)
+    h = p["h"]
+    C0, _ = scf.lowest_orbitals(p["h_host"], nocc)
+    C0 = torch.from_numpy(C0).cuda()
+    D = torch.empty((nao, nao), dtype=torch.float64, device="cuda")
+    J, K = torch.empty_like(D), torch.empty_like(D)
+    en = torch.empty(2, dtype=torch.float64, device="cuda")
+    eb = torch.empty(1, dtype=torch.float64, device="cuda")
+    ctx.df_density(C0, 2.0, D)
+    times, below = adaptive.calibrate(ctx, B, be, C0, 2.0, D, J, K, en, eb, layout=DF_PACKED)
+    log(f"scf: calibration ms {times}; FP64 from level {below} down")
+    runs = {}
+    for name, pol in (("fp64", "fp64"), ("adaptive", "adaptive"), ("fixed_level4", 3)):
+        t0 = time.perf_counter()
+        runs[name] = scf.run_scf(ctx, B, be, h, nocc, n_iter, policy=pol, layout=DF_PACKED,
+                                 fp64_below_level=below)
+        log(f"scf {name}: {time.perf_counter() - t0:.1f} s wall, J/K builds "
+            f"{sum(r['build_ms'] for r in runs[name]):.1f} ms")
+    e_ref = runs["fp64"][-1]["energy"]
+    for a, f, x in zip(runs["adaptive"], runs["fp64"], runs["fixed_level4"]):
+        log(f"it {a['iteration']:2d} level {a['level']} s {a['slices']} {a['build_ms']:.2f} ms "
+            f"E-E_ref {a['energy'] - e_ref:+.2e} | fp64 {f['energy'] - e_ref:+.2e} | "
+            f"level4 {x['energy'] - e_ref:+.2e}")
+    ms_ada = sum(r["build_ms"] for r in runs["adaptive"])
+    ms_fp = sum(r["build_ms"] for r in runs["fp64"])
+    F = flops_alg(nao, naux, nocc)
+    out = {"metric": METRIC, "value": F * n_iter / ms_ada / 1e9, "unit": "TFLOP/s",
+           "n_gpus": 1, "steps": n_iter, "warmup": 1, "ms_per_step": ms_ada / n_iter,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int8 x int8 -> int32, f64 recombination (adaptive), f64 fallback",
+           "data": "synthetic",
+           "config": {"workload": f"synthetic SCF, nao {nao} naux {naux} nocc {nocc}, "
+                                  f"{n_iter} iterations, gapped h, B scaled by "
+                                  f"{dfinputs.scf_two_electron_scale(nao):.4g}, packed B",
+                      "fp64_below_level": below},
+           "calibration_ms": {str(k): v for k, v in times.items()},
+           "adaptive_builds_ms": ms_ada, "fp64_builds_ms": ms_fp,
+           "fixed_level4_builds_ms": sum(r["build_ms"] for r in runs["fixed_level4"]),
+           "speedup_vs_fp64": ms_fp / ms_ada,
+           "final_energy_err_adaptive": runs["adaptive"][-1]["energy"] - e_ref,
+           "final_energy_err_fixed_level4": runs["fixed_level4"][-1]["energy"] - e_ref,
+           "levels_adaptive": [r["level"] for r in runs["adaptive"]],
+           "iterations": runs}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def controller_workload(args):
     """Learned controller vs the plain rule on a 30-iteration sequence."""
     import numpy as np
@@ -423,12 +488,15 @@ def main():
     ap.add_argument("--no-sliced", action="store_true",
                     help="skip the sliced-mode levels (B as digit planes, digit rho and J)")
     ap.add_argument("--cpu-aux", type=int, default=64)
-    ap.add_argument("--workload", choices=("jk", "adaptive", "controller", "batched"),
+    ap.add_argument("--workload", choices=("jk", "adaptive", "controller", "batched", "scf"),
                     default="jk",
                     help="jk: one J/K build per step (default); adaptive: the 20-iteration "
                          "adaptive-precision sequence with metric Cholesky and whitening; "
                          "controller: learned per-block controller vs the plain rule; "
-                         "batched: 48 uneven screened instances, batched vs one by one")
+                         "batched: 48 uneven screened instances, batched vs one by one; "
+                         "scf: synthetic SCF with the adaptive rule vs FP64 and fixed level 4")
+    ap.add_argument("--scf-nao", type=int, default=1024)
+    ap.add_argument("--scf-iters", type=int, default=20)
     ap.add_argument("--ctl-nao", type=int, default=1536,
                     help="nao of the controller evaluation sequence (naux = 4 nao, nocc = nao/8)")
     ap.add_argument("--batch-max-nao", type=int, default=512,
@@ -462,26 +530,54 @@ def main():
         return controller_workload(args)
     if args.workload == "batched":
         return batched_workload(args)
+    if args.workload == "scf":
+        return scf_workload(args)
 
+    from paper_2601_08077_amd import DF_DENSE, DF_PACKED
     cfg = dfinputs.CONFIG1
     nao, naux, nocc = cfg["nao"], cfg["naux"], cfg["nocc"]
     log(f"generating B on the GPU: naux {naux} nao {nao} nocc {nocc}")
     p = dfinputs.make_problem_device(seed=0, **cfg)
-    B, C, D = p["B"], p["C"], p["D"]
+    Bd, C, D = p["B"], p["C"], p["D"]
     ctx = Context()
     ctx.df_set_pblk(64)
     ctx.ensure_workspace(naux, nao, nocc)
     be = torch.empty(naux * nao, dtype=torch.int32, device="cuda")
-    ctx.df_b_exponents(B, be)
     J = torch.empty((nao, nao), dtype=torch.float64, device="cuda")
     K = torch.empty_like(J)
     en = torch.empty(2, dtype=torch.float64, device="cuda")
     eb = torch.empty(1, dtype=torch.float64, device="cuda")
+    # B is stored packed (the lower triangle of every B_P; Sec. 3.3): every
+    # timed build below reads it in that form.  The same builds on the dense
+    # tensor are timed first, for the record, and the dense copy is dropped.
+    ctx.df_b_exponents(Bd, be)
     torch.cuda.synchronize()
     assert ctx.df_get_status() == 0
+    dense_rec = {}
+    for s_ in (0, args.slices):
+        ctx.df_set_precision(s_)
+        ctx.df_build_jk(Bd, be, C, 2.0, D, J, K, en, eb)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.sweep_reps):
+            ctx.df_build_jk(Bd, be, C, 2.0, D, J, K, en, eb)
+        e1.record()
+        torch.cuda.synchronize()
+        dense_rec["fp64_ms" if s_ == 0 else f"s{s_}_ms"] = e0.elapsed_time(e1) / args.sweep_reps
+    log(f"dense B: {dense_rec}")
+    B = dfinputs.pack_lower(Bd)
+    del Bd, p["B"]
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    be_p = torch.empty_like(be)
+    ctx.df_b_exponents(B, be_p, layout=DF_PACKED)
+    torch.cuda.synchronize()
+    assert ctx.df_get_status() == 0
+    assert torch.equal(be_p, be), "packed and dense row exponents differ"
 
     def build():
-        ctx.df_build_jk(B, be, C, 2.0, D, J, K, en, eb)
+        ctx.df_build_jk(B, be, C, 2.0, D, J, K, en, eb, layout=DF_PACKED)
 
     def timed(s, steps, warmup, stages=False, fn=build):
         ctx.df_set_precision(s)
@@ -540,7 +636,7 @@ def main():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        ctx.df_prepare_b(B, planes, be2, dig)
+        ctx.df_prepare_b(B, planes, be2, dig, layout=DF_PACKED)
         e1.record()
         torch.cuda.synchronize()
         assert ctx.df_get_status() == 0
@@ -596,7 +692,8 @@ def main():
         "dtype": "int8 x int8 -> int32, f64 recombination" if s else "f64",
         "data": "synthetic",
         "config": {"workload": "DF J/K build, nao 768 naux 3072 nocc 96, L 24, per-aux scale "
-                               "1e-6..1, dense B resident in HBM",
+                               "1e-6..1, packed B (lower triangles, 7.26 GB) resident in HBM",
+                   "layout": "DF_PACKED",
                    "slices": s, "pblk": 64, "k_groups": ctx.df_get_k_groups(),
                    "flops_alg": F, "flops_paper_convention": Fp},
         "paper_convention_tflops": Fp / ms / 1e9,
@@ -611,6 +708,7 @@ def main():
         "peaks_measured": peaks,
         "sweep": sweep,
         "sliced_mode": {"prepare_b_ms": sliced_prep_ms, "planes": 8, "levels": sliced},
+        "dense_b": dense_rec,
     }
     if not args.no_cpu:
         log(f"cpu baseline: oracle on {args.cpu_aux} aux rows")

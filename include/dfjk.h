@@ -60,8 +60,19 @@ enum df_status {
   DF_ENOTSPD = -6          /* non-positive pivot in the metric Cholesky (device)  */
 };
 
+/* Storage of the three-index tensor B (every B_P is symmetric):
+ *   DF_DENSE  [naux][nao][nao], both triangles.
+ *   DF_PACKED [naux][nao (nao + 1) / 2], the lower triangle of each B_P by
+ *             rows: element (mu, nu), mu >= nu, at mu (mu + 1) / 2 + nu (the
+ *             stored form of Sec. 3.3; half the bytes).  nao <= 16383.  Taken
+ *             by df_b_exponents, df_build_x, df_build_jk, df_prepare_b and
+ *             df_debug_build_i32; results are bit-identical to
+ *             the same build on the dense tensor, except rho (and so J and E_J),
+ *             which may differ in FP64 rounding order.  Screening, the
+ *             autotuner, the batched build and df_spot_check take DF_DENSE. */
 enum df_layout {
-  DF_DENSE = 0             /* B as [naux][nao][nao]                               */
+  DF_DENSE = 0,
+  DF_PACKED = 1
 };
 
 typedef struct df_ctx df_ctx;
@@ -104,6 +115,17 @@ int df_set_pblk(df_ctx* ctx, int pblk);
 int df_set_k_groups(df_ctx* ctx, int groups);
 int df_get_k_groups(const df_ctx* ctx);
 
+/* Digit-pair scheme of the emulated products: extra = 0 forms the pairs
+ * a + b <= s + 1 (s(s+1)/2 INT8 products; Sec. 3.2, Eq. 8), extra = 1 also
+ * the anti-diagonal a + b = s + 2 (s - 1 more products, a, b <= s): the
+ * dropped-pair error shrinks, so the stated bound is tighter at s <= 7 for the
+ * same slice count (an alternative scheme along the outlook of Sec. 5 on
+ * choosing slice counts; at s = 1 there is nothing to add).  Applies to
+ * df_build_jk, df_build_x and df_debug_build_i32 (which then exports s + 1
+ * anti-diagonals); df_build_jk_sliced returns DF_EINVAL while extra = 1.
+ * DF_EINVAL outside 0..1. */
+int df_set_extra_pairs(df_ctx* ctx, int extra);
+
 /* Depth of the nu chunk that one step of the INT8 X product stages in LDS:
  * 1 = 64 (two LDS stages, the default), 2 = 128 (one stage; used only where
  * slices <= 5 and nao is a multiple of 128, else 64), 0 = the autotuned choice
@@ -138,7 +160,8 @@ int df_build_x(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t n
                const int32_t* b_exp, const double* C, int64_t nocc, double* X);
 
 /* The whole build at the context precision (Eqs. 3-6).
- *   B       [naux][nao][nao] (layout DF_DENSE), symmetric in the last two indices
+ *   B       [naux][nao][nao] (DF_DENSE) or [naux][nao (nao + 1) / 2] (DF_PACKED),
+ *           symmetric in the last two indices
  *   b_exp   [naux*nao] from df_b_exponents, or NULL
  *   C       [nao][nocc];  occ the occupation factor (2 for closed shells)
  *   D       [nao][nao], the density occ * C C^T used for rho (Eq. 3); symmetric, like
@@ -268,6 +291,16 @@ int df_whiten(df_ctx* ctx, const double* L, int64_t naux, const double* T, int64
 /* Density of closed-shell orbitals: D = occ * C C^T (D [nao][nao], C [nao][nocc])
  * in FP64 on the context stream.  Needs no workspace. */
 int df_density(df_ctx* ctx, const double* C, int64_t nao, int64_t nocc, double occ, double* D);
+
+/* Fock matrix of a closed-shell SCF iteration around the build (the SCF of
+ * Sec. 4.3 in which the precision rule runs; overlap taken as the identity):
+ * F = h + J - K / 2 elementwise (F[i] = (h[i] + J[i]) - 0.5 K[i]) and
+ * e_one[0] = tr(D h) (device scalar; a fixed summation order), with h, J, K,
+ * D, F [nao][nao] device arrays (F may alias none of the inputs).  The total
+ * energy of the iteration is e_one + E_J + E_x.  Uses the context's scratch;
+ * needs no workspace. */
+int df_fock(df_ctx* ctx, const double* h, const double* J, const double* K, const double* D,
+            int64_t nao, double* F, double* e_one);
 
 /* Adaptive precision rule of Sec. 3.2 (Eq. 11, Table 1); host-only, no GPU work.
  *   df_rule_level(de_rel): Table 1 level for a relative energy change
@@ -413,7 +446,8 @@ int df_peak_probe(df_ctx* ctx, int kind, void* buf, size_t bytes, int iters, dou
  * per-block counts; same arguments as df_build_jk's X inputs, workspace of
  * df_workspace_size) and exports, before recombination,
  *   x_sums[g-2][P*nao + mu][i] = S_g of row (P, mu) of B and column i of C,
- *     the sum over the pairs a + b = g (g = 2..s+1) of the digit products
+ *     the sum over the pairs a + b = g (g = 2..s+1, ..s+2 with extra pairs,
+ *     df_set_extra_pairs) of the digit products
  *     (Sec. 3.2, Eq. 8), as accumulated by the X tiles;
  *   k_sums[g-2][b][mu][nu] = S_g of rows mu and nu of X_b (aux block b of
  *     pblk indices, nb = ceil(naux / pblk) blocks), as accumulated by the K

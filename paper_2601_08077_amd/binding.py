@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(_HERE, "libdfjk.so")
 
 DF_OK, DF_EINVAL, DF_EWORKSPACE, DF_EHIP, DF_ENONFINITE, DF_EOVERFLOW_GUARD, DF_ENOTSPD = (
     0, -1, -2, -3, -4, -5, -6)
-DF_DENSE = 0
+DF_DENSE, DF_PACKED = 0, 1
 STAGES = ("bexp", "prep", "x", "slice_x", "k", "k_reduce", "rho", "j", "energies", "bound")
 
 _c_void_p = ctypes.c_void_p
@@ -39,6 +39,7 @@ SIGNATURES = {
     "df_set_block_precision": (_int, [_c_void_p, ctypes.POINTER(ctypes.c_int32), _i64]),
     "df_get_k_groups": (_int, [_c_void_p]),
     "df_set_x_ksub": (_int, [_c_void_p, _int]),
+    "df_set_extra_pairs": (_int, [_c_void_p, _int]),
     "df_workspace_size": (_int, [_c_void_p, _i64, _i64, _i64, _int, ctypes.POINTER(ctypes.c_size_t)]),
     "df_set_workspace": (_int, [_c_void_p, _c_void_p, ctypes.c_size_t]),
     "df_b_exponents": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _c_void_p]),
@@ -85,6 +86,8 @@ SIGNATURES = {
     "df_metric_cholesky": (_int, [_c_void_p, _c_void_p, _i64]),
     "df_whiten": (_int, [_c_void_p, _c_void_p, _i64, _c_void_p, _i64, _c_void_p]),
     "df_density": (_int, [_c_void_p, _c_void_p, _i64, _i64, ctypes.c_double, _c_void_p]),
+    "df_fock": (_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p,
+                       _c_void_p]),
     "df_rule_level": (_int, [ctypes.c_double]),
     "df_rule_next_level": (_int, [_int, ctypes.c_double, ctypes.c_double]),
     "df_rule_slices": (_int, [_int, _int]),
@@ -129,6 +132,23 @@ class DFError(RuntimeError):
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _shape(B, layout, naux=None, nao=None):
+    """(naux, nao) of B: [naux][nao][nao] (DF_DENSE) or [naux][nao (nao + 1) / 2]
+    (DF_PACKED; nao follows from the packed length unless given)."""
+    if naux is None:
+        naux = B.shape[0]
+    if nao is None:
+        if layout == DF_PACKED:
+            import math
+            npair = B.shape[1]
+            nao = (math.isqrt(8 * npair + 1) - 1) // 2
+            if nao * (nao + 1) // 2 != npair:
+                raise ValueError("packed B: the row length is not a triangular number")
+        else:
+            nao = B.shape[1]
+    return int(naux), int(nao)
 
 
 class Context:
@@ -185,6 +205,9 @@ class Context:
         self._check(self.lib.df_set_block_precision(self.h, arr, len(s_blocks)),
                     "df_set_block_precision")
 
+    def df_set_extra_pairs(self, extra):
+        self._check(self.lib.df_set_extra_pairs(self.h, int(extra)), "df_set_extra_pairs")
+
     def df_set_x_ksub(self, ksub):
         self._check(self.lib.df_set_x_ksub(self.h, int(ksub)), "df_set_x_ksub")
 
@@ -212,8 +235,8 @@ class Context:
         return need
 
     # -- compute entry points -------------------------------------------------
-    def df_b_exponents(self, B, b_exp, layout=DF_DENSE):
-        naux, nao = B.shape[0], B.shape[1]
+    def df_b_exponents(self, B, b_exp, layout=DF_DENSE, naux=None, nao=None):
+        naux, nao = _shape(B, layout, naux, nao)
         self._check(self.lib.df_b_exponents(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp)),
                     "df_b_exponents")
 
@@ -222,21 +245,22 @@ class Context:
         self._check(self.lib.df_slice(self.h, _ptr(A), rows, cols, A.stride(0), int(slices),
                                       _ptr(digits), _ptr(row_exp)), "df_slice")
 
-    def df_build_x(self, B, b_exp, C, X, layout=DF_DENSE):
-        naux, nao = B.shape[0], B.shape[1]
+    def df_build_x(self, B, b_exp, C, X, layout=DF_DENSE, naux=None, nao=None):
+        naux, nao = _shape(B, layout, naux, nao)
         self._check(self.lib.df_build_x(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp), _ptr(C),
                                         C.shape[1], _ptr(X)), "df_build_x")
 
-    def df_build_jk(self, B, b_exp, C, occ, D, J, K, energies, err_bound, layout=DF_DENSE):
-        naux, nao = B.shape[0], B.shape[1]
+    def df_build_jk(self, B, b_exp, C, occ, D, J, K, energies, err_bound, layout=DF_DENSE,
+                    naux=None, nao=None):
+        naux, nao = _shape(B, layout, naux, nao)
         self._check(self.lib.df_build_jk(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp), _ptr(C),
                                          C.shape[1], float(occ), _ptr(D), _ptr(J), _ptr(K),
                                          _ptr(energies), _ptr(err_bound)), "df_build_jk")
 
-    def df_prepare_b(self, B, planes, b_exp, b_dig, layout=DF_DENSE):
+    def df_prepare_b(self, B, planes, b_exp, b_dig, layout=DF_DENSE, naux=None, nao=None):
         """b_exp [naux*nao] int32, b_dig [planes][naux*nao][ldk] int8 (ldk = nao
         rounded up to 64); sizes from df_prepare_b_size."""
-        naux, nao = B.shape[0], B.shape[1]
+        naux, nao = _shape(B, layout, naux, nao)
         self._check(self.lib.df_prepare_b(self.h, _ptr(B), layout, naux, nao, int(planes),
                                           _ptr(b_exp), _ptr(b_dig)), "df_prepare_b")
 
@@ -360,6 +384,11 @@ class Context:
                                            ctypes.byref(r)), "df_peak_probe")
         return r.value
 
+    def df_fock(self, h, J, K, D, F, e_one):
+        """F = h + J - K / 2 and e_one[0] = tr(D h) on the device."""
+        self._check(self.lib.df_fock(self.h, _ptr(h), _ptr(J), _ptr(K), _ptr(D), h.shape[0],
+                                     _ptr(F), _ptr(e_one)), "df_fock")
+
     def df_timing_begin(self, max_calls):
         self._check(self.lib.df_timing_begin(self.h, int(max_calls)), "df_timing_begin")
 
@@ -373,9 +402,10 @@ class Context:
     def df_get_status(self):
         return self.lib.df_get_status(self.h)
 
-    def df_debug_build_i32(self, B, b_exp, C, x_sums, k_sums, layout=DF_DENSE):
+    def df_debug_build_i32(self, B, b_exp, C, x_sums, k_sums, layout=DF_DENSE, naux=None,
+                           nao=None):
         """x_sums int32 [s][naux*nao][nocc], k_sums int32 [s][nb][nao][nao]."""
-        naux, nao = B.shape[0], B.shape[1]
+        naux, nao = _shape(B, layout, naux, nao)
         self._check(self.lib.df_debug_build_i32(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp),
                                                 _ptr(C), C.shape[1], _ptr(x_sums), _ptr(k_sums)),
                     "df_debug_build_i32")

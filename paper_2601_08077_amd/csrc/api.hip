@@ -20,6 +20,7 @@ struct df_ctx {
   int k_groups_req = 0;
   int k_groups_used = 0;
   int x_ksub_req = 0;  // X chunk depth asked for (0 = autotuned or default)
+  int extra = 0;       // anti-diagonals of digit pairs kept beyond a + b = s + 1
   int ncu = 256;  // compute units of the context's device
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -80,6 +81,7 @@ struct Plan {
   int64_t naux, nao, nocc;
   int pblk, nb, nao_pad, kbp, ncp, kp, groups, jsplit;
   int naux_pad, jdsplit;
+  int packed;  // B stored as DF_PACKED (set by common_checks)
   size_t off_bexp, off_fcol, off_dC, off_X, off_xmax, off_F, off_Xd, off_rho, off_rowdot,
       off_Jp, off_Kp, off_bsc, off_esc, off_dD, off_gexp, off_h, off_wd, off_Sj, off_drho,
       off_Xs, off_Ks, off_xsmax, total;
@@ -178,7 +180,10 @@ Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
 
 int check_shape(df_ctx* c, int layout, int64_t naux, int64_t nao, int64_t nocc) {
   if (!c) return DF_EINVAL;
-  if (layout != DF_DENSE) return fail(c, DF_EINVAL, "layout: only DF_DENSE is supported");
+  if (layout != DF_DENSE && layout != DF_PACKED)
+    return fail(c, DF_EINVAL, "layout must be DF_DENSE or DF_PACKED");
+  if (layout == DF_PACKED && nao > 16383)
+    return fail(c, DF_EINVAL, "DF_PACKED supports nao <= 16383");
   if (naux < 1 || nao < 1 || nocc < 1) return fail(c, DF_EINVAL, "naux, nao and nocc must be >= 1");
   if (nao > 65536 || nocc > 65536 || naux > (int64_t)1 << 31)
     return fail(c, DF_EINVAL, "dimension too large");
@@ -238,7 +243,7 @@ int run_x(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp, const
   DF_HIP(launch_fill_u64(c->stream, xmax, (int64_t)p.nb * p.nao, 0ull), "fill xmax");
   if (s == 0) {
     DF_HIP(launch_x_fp64(c->stream, B, p.naux, (int)p.nao, C, (int)p.nocc, X, 0, xmax, p.pblk,
-                         nullptr, nullptr, chunks_for(c, p.nao)),
+                         nullptr, nullptr, chunks_for(c, p.nao), p.packed),
            "x_fp64");
     return DF_OK;
   }
@@ -248,7 +253,7 @@ int run_x(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp, const
   DF_HIP(launch_slice_c(c->stream, C, p.nao, p.nocc, s, fcol, p.ncp, p.kp, 0, dC), "slice_c");
   DF_HIP(launch_x_int8(c->stream, s, B, p.naux, (int)p.nao, b_exp, dC, p.ncp, p.kp, fcol,
                        (int)p.nocc, X, 0, xmax, p.pblk, nullptr, nullptr, chunks_for(c, p.nao),
-                       ksub_for(c, p.naux, p.nao, p.nocc)),
+                       ksub_for(c, p.naux, p.nao, p.nocc), nullptr, p.packed, c->extra),
          "x_int8");
   return DF_OK;
 }
@@ -275,7 +280,9 @@ int k_stages(df_ctx* c, const Plan& p, const double* X, double occ, double* K, i
   if (s == 0) {
     DF_HIP(launch_k_fp64(st, X, naux, (int)nao, (int)nocc, p.pblk, p.nb, p.groups, Kp), "k_fp64");
   } else {
-    DF_HIP(launch_k_int8(st, s, Xd, F, p.nb, (int)nao, p.nao_pad, p.kbp, p.groups, Kp), "k_int8");
+    DF_HIP(launch_k_int8(st, s, Xd, F, p.nb, (int)nao, p.nao_pad, p.kbp, p.groups, Kp, nullptr,
+                         c->extra),
+           "k_int8");
   }
   mark(c, 1 + DF_STAGE_K);
   c->k_groups_used = p.groups;
@@ -293,13 +300,13 @@ int k_bound_stage(df_ctx* c, const Plan& p, const int32_t* b_exp, const int32_t*
   const int64_t naux = p.naux, nao = p.nao, nocc = p.nocc;
   const int64_t kb_full = (int64_t)p.pblk * nocc;
   const int64_t kb_last = (naux - (int64_t)(p.nb - 1) * p.pblk) * nocc;
-  const double k1 = kappa_of(s, nao);
-  const double k2f = s ? kappa_of(s, kb_full) : kappa_of(0, naux * nocc);
-  const double k2l = s ? kappa_of(s, kb_last) : kappa_of(0, naux * nocc);
+  const double k1 = kappa_of(s, nao, c->extra);
+  const double k2f = s ? kappa_of(s, kb_full, c->extra) : kappa_of(0, naux * nocc);
+  const double k2l = s ? kappa_of(s, kb_last, c->extra) : kappa_of(0, naux * nocc);
   const int32_t* sblk = c->blk_s.empty() ? nullptr : c->blk_dev;
   DF_HIP(launch_bound(c->stream, b_exp, fcol, (int)nocc, at<int32_t>(c, p.off_F), fstride, naux,
                       (int)nao, p.pblk, p.nb, k1, k2f, k2l, occ, sblk, at<double>(c, p.off_bsc),
-                      err_bound),
+                      err_bound, c->extra),
          "bound");
   return DF_OK;
 }
@@ -348,16 +355,16 @@ int xk_stages_blocks(df_ctx* c, const Plan& p, const double* B, const int32_t* b
   for (const Run& r : runs) {
     const int64_t P0 = (int64_t)r.b0 * p.pblk;
     const int64_t P1 = std::min<int64_t>((int64_t)r.b1 * p.pblk, naux);
-    const double* Bp = B + P0 * nn;
+    const double* Bp = B + P0 * (p.packed ? nao * (nao + 1) / 2 : nn);
     double* Xr = X + P0 * nao * nocc;  // the blocked layout keeps each block contiguous
     if (r.s == 0) {
       DF_HIP(launch_x_fp64(st, Bp, P1 - P0, (int)nao, C, (int)nocc, Xr, 1, xmax + r.b0 * nao,
-                           p.pblk, D, rowdot + P0 * nao, chunks_for(c, nao)),
+                           p.pblk, D, rowdot + P0 * nao, chunks_for(c, nao), p.packed),
              "x_fp64");
     } else {
       DF_HIP(launch_x_int8(st, r.s, Bp, P1 - P0, (int)nao, b_exp + P0 * nao, dC, p.ncp, p.kp, fcol,
                            (int)nocc, Xr, 1, xmax + r.b0 * nao, p.pblk, D, rowdot + P0 * nao,
-                           chunks_for(c, nao)),
+                           chunks_for(c, nao), 0, nullptr, p.packed, c->extra),
              "x_int8");
     }
   }
@@ -380,7 +387,7 @@ int xk_stages_blocks(df_ctx* c, const Plan& p, const double* B, const int32_t* b
                             xmax + (int64_t)r.b0 * nao, F + (int64_t)r.b0 * p.nao_pad, Xd),
              "slice_x");
       DF_HIP(launch_k_int8(st, r.s, Xd, F + (int64_t)r.b0 * p.nao_pad, nbr, (int)nao, p.nao_pad,
-                           p.kbp, nbr, Kp + (int64_t)r.b0 * nn),
+                           p.kbp, nbr, Kp + (int64_t)r.b0 * nn, nullptr, c->extra),
              "k_int8");
     }
   }
@@ -399,9 +406,19 @@ int common_checks(df_ctx* c, const double* B, int layout, int64_t naux, int64_t 
   if (!B || !C) return fail(c, DF_EINVAL, "null B or C");
   rc = check_guard(c, effective_max_slices(c), nao, nocc);
   if (rc) return rc;
+  if (layout == DF_PACKED && chunks_for(c, nao))
+    return fail(c, DF_EINVAL, "screening masks apply to DF_DENSE B only");
   p = make_plan(c, naux, nao, nocc);
+  p.packed = layout == DF_PACKED;
   if (!c->ws || c->ws_bytes < p.total) return fail(c, DF_EWORKSPACE, "workspace too small");
   return DF_OK;
+}
+
+// Row exponents of B (dense or packed) into b_exp.
+hipError_t launch_bexp(df_ctx* c, const double* B, int packed, int64_t naux, int64_t nao,
+                       int32_t* b_exp) {
+  if (packed) return launch_row_exp_packed(c->stream, B, naux, (int)nao, b_exp, c->status);
+  return launch_row_exp(c->stream, B, naux * nao, nao, nao, b_exp, c->status);
 }
 
 }  // namespace
@@ -513,6 +530,13 @@ int df_set_block_precision(df_ctx* c, const int32_t* host_s, int64_t nblocks) {
 
 int df_get_k_groups(const df_ctx* c) { return c ? c->k_groups_used : DF_EINVAL; }
 
+int df_set_extra_pairs(df_ctx* c, int extra) {
+  if (!c) return DF_EINVAL;
+  if (extra < 0 || extra > 1) return fail(c, DF_EINVAL, "extra must be 0 or 1");
+  c->extra = extra;
+  return DF_OK;
+}
+
 int df_set_x_ksub(df_ctx* c, int ksub) {
   if (!c) return DF_EINVAL;
   if (ksub < 0 || ksub > 2) return fail(c, DF_EINVAL, "ksub must be 0, 1 or 2");
@@ -544,7 +568,7 @@ int df_b_exponents(df_ctx* c, const double* B, int layout, int64_t naux, int64_t
   const int rc = check_shape(c, layout, naux, nao, 1);
   if (rc) return rc;
   if (!B || !b_exp) return fail(c, DF_EINVAL, "null pointer");
-  DF_HIP(launch_row_exp(c->stream, B, naux * nao, nao, nao, b_exp, c->status), "row_exp");
+  DF_HIP(launch_bexp(c, B, layout == DF_PACKED, naux, nao, b_exp), "row_exp");
   return DF_OK;
 }
 
@@ -570,7 +594,7 @@ int df_build_x(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao
   if (!X) return fail(c, DF_EINVAL, "null X");
   if (c->slices > 0 && !b_exp) {
     int32_t* be = at<int32_t>(c, p.off_bexp);
-    DF_HIP(launch_row_exp(c->stream, B, naux * nao, nao, nao, be, c->status), "row_exp");
+    DF_HIP(launch_bexp(c, B, p.packed, naux, nao, be), "row_exp");
     b_exp = be;
   }
   return run_x(c, p, B, b_exp, C, X);
@@ -593,7 +617,7 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
   mark(c, 0);
   if (!b_exp) {
     int32_t* be = at<int32_t>(c, p.off_bexp);
-    DF_HIP(launch_row_exp(st, B, naux * nao, nao, nao, be, c->status), "row_exp");
+    DF_HIP(launch_bexp(c, B, p.packed, naux, nao, be), "row_exp");
     b_exp = be;
   }
   mark(c, 1 + DF_STAGE_BEXP);
@@ -613,11 +637,12 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
     if (rc) return rc;
   } else if (s == 0) {
     DF_HIP(launch_x_fp64(st, B, naux, (int)nao, C, (int)nocc, X, 1, xmax, p.pblk, D, rowdot,
-                         chunks_for(c, nao)),
+                         chunks_for(c, nao), p.packed),
            "x_fp64");
   } else {
     DF_HIP(launch_x_int8(st, s, B, naux, (int)nao, b_exp, dC, p.ncp, p.kp, fcol, (int)nocc, X, 1,
-                         xmax, p.pblk, D, rowdot, chunks_for(c, nao), ksub_for(c, naux, nao, nocc)),
+                         xmax, p.pblk, D, rowdot, chunks_for(c, nao), ksub_for(c, naux, nao, nocc),
+                         nullptr, p.packed, c->extra),
            "x_int8");
   }
   if (!per_block) {
@@ -629,7 +654,7 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
   DF_HIP(launch_rho_reduce(st, rowdot, naux, (int)nao, rho), "rho_reduce");
   mark(c, 1 + DF_STAGE_RHO);
   DF_HIP(launch_j(st, B, naux, (int)nao, rho, p.jsplit, at<double>(c, p.off_Jp), J,
-                  mask_for(c, nao), c->scr_blk),
+                  mask_for(c, nao), c->scr_blk, p.packed),
          "j");
   mark(c, 1 + DF_STAGE_J);
   DF_HIP(launch_energies(st, rho, naux, D, K, (int)nao, at<double>(c, p.off_esc), energies),
@@ -658,9 +683,9 @@ int df_prepare_b(df_ctx* c, const double* B, int layout, int64_t naux, int64_t n
   if (!B || !b_exp || !b_dig) return fail(c, DF_EINVAL, "null pointer");
   if (planes < 1 || planes > kMaxSlices) return fail(c, DF_EINVAL, "planes must be 1..8");
   if (reinterpret_cast<uintptr_t>(b_dig) & 15) return fail(c, DF_EINVAL, "b_dig must be 16-byte aligned");
-  DF_HIP(launch_row_exp(c->stream, B, naux * nao, nao, nao, b_exp, c->status), "row_exp");
+  DF_HIP(launch_bexp(c, B, layout == DF_PACKED, naux, nao, b_exp), "row_exp");
   DF_HIP(launch_slice_planes(c->stream, B, naux * nao, (int)nao, (int)round_up(nao, 64), b_exp,
-                             planes, b_dig),
+                             planes, b_dig, layout == DF_PACKED),
          "slice_planes");
   return DF_OK;
 }
@@ -674,6 +699,7 @@ int df_build_jk_sliced(df_ctx* c, const int8_t* b_dig, int planes, const int32_t
   if (rc) return rc;
   const int s = c->slices;
   if (!c->blk_s.empty()) return fail(c, DF_EINVAL, "the sliced build uses one slice count: reset block precision");
+  if (c->extra) return fail(c, DF_EINVAL, "the sliced build forms the plain digit pairs only: set extra pairs to 0");
   if (planes < 1 || planes > kMaxSlices) return fail(c, DF_EINVAL, "planes must be 1..8");
   if (s < 1 || s > planes) return fail(c, DF_EINVAL, "the sliced build needs 1 <= slices <= planes");
   if (!b_dig || !b_exp || !C || !D || !J || !K || !energies || !err_bound)
@@ -1253,6 +1279,17 @@ int df_density(df_ctx* c, const double* C, int64_t nao, int64_t nocc, double occ
   return DF_OK;
 }
 
+int df_fock(df_ctx* c, const double* h, const double* J, const double* K, const double* D,
+            int64_t nao, double* F, double* e_one) {
+  clear_stale_error();
+  if (!c) return DF_EINVAL;
+  if (!h || !J || !K || !D || !F || !e_one || nao < 1 || nao > 65536)
+    return fail(c, DF_EINVAL, "bad arguments");
+  DF_HIP(launch_fock(c->stream, h, J, K, D, nao, F, reinterpret_cast<double*>(c->aux), e_one),
+         "fock");
+  return DF_OK;
+}
+
 int df_rule_level(double de_rel) {
   if (de_rel != de_rel) return 4;
   if (de_rel >= 2e-6) return 4;
@@ -1355,7 +1392,7 @@ int df_debug_build_i32(df_ctx* c, const double* B, int layout, int64_t naux, int
   hipStream_t st = c->stream;
   if (!b_exp) {
     int32_t* be = at<int32_t>(c, p.off_bexp);
-    DF_HIP(launch_row_exp(st, B, naux * nao, nao, nao, be, c->status), "row_exp");
+    DF_HIP(launch_bexp(c, B, p.packed, naux, nao, be), "row_exp");
     b_exp = be;
   }
   double* X = at<double>(c, p.off_X);
@@ -1367,14 +1404,14 @@ int df_debug_build_i32(df_ctx* c, const double* B, int layout, int64_t naux, int
   DF_HIP(launch_slice_c(st, C, nao, nocc, s, fcol, p.ncp, p.kp, 0, dC), "slice_c");
   DF_HIP(launch_x_int8(st, s, B, naux, (int)nao, b_exp, dC, p.ncp, p.kp, fcol, (int)nocc, X, 1,
                        xmax, p.pblk, nullptr, nullptr, chunks_for(c, nao),
-                       ksub_for(c, naux, nao, nocc), x_sums),
+                       ksub_for(c, naux, nao, nocc), x_sums, p.packed, c->extra),
          "x_int8");
   int32_t* F = at<int32_t>(c, p.off_F);
   int8_t* Xd = at<int8_t>(c, p.off_Xd);
   DF_HIP(launch_slice_x(st, s, X, naux, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp, xmax, F, Xd),
          "slice_x");
   DF_HIP(launch_k_int8(st, s, Xd, F, p.nb, (int)nao, p.nao_pad, p.kbp, p.groups,
-                       at<double>(c, p.off_Kp), k_sums),
+                       at<double>(c, p.off_Kp), k_sums, c->extra),
          "k_int8");
   return DF_OK;
 }

@@ -57,19 +57,24 @@ __device__ __forceinline__ uint32_t digit_byte(uint64_t w, int k) {
 //   |Z - Z_hat| <= k 2^(e_r + f_c) kappa.
 // s >= 1: slicing of both operands (2 eps + eps^2, eps the largest dropped
 // tail of a balanced base-256 expansion plus the 62-bit truncation), the digit
-// pairs with a + b >= s + 2 that are not formed (2s + 1 - g pairs of weight
-// 2^(18 - 8g) at each g), and the s - 1 FP64 roundings of the recombination.
-__host__ __device__ inline double kappa_of(int s, int64_t k) {
+// pairs with a + b >= s + 2 + extra that are not formed (2s + 1 - g pairs of
+// weight 2^(18 - 8g) at each g), and the s + extra - 1 FP64 roundings of the
+// recombination.  extra (the anti-diagonals kept beyond s + 1) is clamped to
+// 0..s-1.
+__host__ __device__ inline double kappa_of(int s, int64_t k, int extra = 0) {
   const double u = 0x1p-53;
   if (s == 0) {
     const double ku = (double)k * u;
     return ku / (1.0 - ku);
   }
+  const int ex = extra < 0 ? 0 : (extra > s - 1 ? s - 1 : extra);
   const double eps = (128.0 / 255.0) * ldexp(1.0, 2 - 8 * s) * (1.0 - ldexp(1.0, -8 * (8 - s))) +
                      0x1p-62;
   double dropped = 0.0;
-  for (int g = s + 2; g <= 2 * s; ++g) dropped += (double)(2 * s + 1 - g) * ldexp(1.0, 18 - 8 * g);
-  const double rounding = (s - 1) * u * 1.016 * pow(1.0 + u, (double)s);
+  for (int g = s + 2 + ex; g <= 2 * s; ++g)
+    dropped += (double)(2 * s + 1 - g) * ldexp(1.0, 18 - 8 * g);
+  const int nadd = s + ex - 1;
+  const double rounding = nadd * u * 1.016 * pow(1.0 + u, (double)(nadd + 1));
   return 2.0 * eps + eps * eps + dropped + rounding;
 }
 
@@ -138,6 +143,9 @@ namespace dfjk {
 // slicing.hip
 hipError_t launch_row_exp(hipStream_t st, const double* A, int64_t rows, int64_t cols,
                           int64_t lda, int32_t* e, int* status);
+// Row exponents of a packed B ([naux][nao (nao + 1) / 2], lower triangles by rows).
+hipError_t launch_row_exp_packed(hipStream_t st, const double* B, int64_t naux, int nao,
+                                 int32_t* e, int* status);
 hipError_t launch_col_exp(hipStream_t st, const double* C, int64_t nao, int64_t nocc,
                           int32_t* f, int* status);
 hipError_t launch_slice_rows(hipStream_t st, const double* A, int64_t rows, int64_t cols,
@@ -158,10 +166,12 @@ hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, i
                          const int32_t* f_col, int nocc, double* X, int xlayout,
                          unsigned long long* xmax, int pblk, const double* D, double* rowdot,
                          const unsigned long long* cmask = nullptr, int ksub = 0,
-                         int32_t* dbg = nullptr);
+                         int32_t* dbg = nullptr, int packed = 0, int extra = 0);
 // (ksub: k depth per LDS stage, 1 = 64, 2 = 128 where s <= 5 and nao % 128 == 0,
 // 0 = the default choice.  dbg, a test export: [s][naux*nao][nocc] int32
-// anti-diagonal sums g = 2..s+1 of the tiles.)
+// anti-diagonal sums g = 2..s+1 of the tiles.  packed: B as [naux][nao(nao+1)/2],
+// the lower triangle of each B_P by rows (no screening masks; 64-wide chunks).
+// extra: anti-diagonals kept beyond a + b = s + 1 (0 or 1; 64-wide chunks).)
 // X in the blocked layout.
 hipError_t launch_slice_x(hipStream_t st, int s, const double* Xb, int64_t naux, int nao,
                           int nocc, int pblk, int nao_pad, int kbp,
@@ -172,7 +182,7 @@ int k_int8_resident(int s);
 // per aux block, written where mu / 64 >= nu / 64 (the lower tiles).
 hipError_t launch_k_int8(hipStream_t st, int s, const int8_t* Xd, const int32_t* F, int nb,
                          int nao, int nao_pad, int kbp, int groups, double* Kp,
-                         int32_t* dbg = nullptr);
+                         int32_t* dbg = nullptr, int extra = 0);
 hipError_t launch_debug_pairs(hipStream_t st, int s, const int8_t* a_dig, const int8_t* b_dig,
                               int64_t m, int64_t n, int64_t k, int8_t* ws_a, int8_t* ws_b,
                               int32_t* partials);
@@ -181,7 +191,7 @@ hipError_t launch_debug_pairs(hipStream_t st, int s, const int8_t* a_dig, const 
 hipError_t launch_x_fp64(hipStream_t st, const double* B, int64_t naux, int nao,
                          const double* C, int nocc, double* X, int xlayout,
                          unsigned long long* xmax, int pblk, const double* D, double* rowdot,
-                         const unsigned long long* cmask = nullptr);
+                         const unsigned long long* cmask = nullptr, int packed = 0);
 // X in the blocked layout.
 hipError_t launch_k_fp64(hipStream_t st, const double* Xb, int64_t naux, int nao, int nocc,
                          int pblk, int nb, int groups, double* Kp);
@@ -205,9 +215,13 @@ hipError_t launch_rho_reduce(hipStream_t st, const double* rowdot, int64_t naux,
 // With smask ([nblk][nblk] kept shell blocks of size blk), dropped blocks are
 // not read (they are zero in the screened B).
 hipError_t launch_j(hipStream_t st, const double* B, int64_t naux, int nao, const double* rho,
-                    int jsplit, double* Jp, double* J, const uint8_t* smask = nullptr, int blk = 8);
+                    int jsplit, double* Jp, double* J, const uint8_t* smask = nullptr, int blk = 8,
+                    int packed = 0);
 hipError_t launch_k_reduce(hipStream_t st, const double* Kp, int groups, int nao, double occ,
                            double* K);
+// F = h + J - K / 2 and e_one = tr(D h) (scratch: 256 doubles).
+hipError_t launch_fock(hipStream_t st, const double* h, const double* J, const double* K,
+                       const double* D, int64_t nao, double* F, double* scratch, double* e_one);
 // scratch: 2 * 256 doubles.
 hipError_t launch_energies(hipStream_t st, const double* rho, int64_t naux, const double* D,
                            const double* K, int nao, double* scratch, double* energies);
@@ -216,13 +230,14 @@ hipError_t launch_energies(hipStream_t st, const double* rho, int64_t naux, cons
 hipError_t launch_bound(hipStream_t st, const int32_t* b_exp, const int32_t* f_col, int nocc,
                         const int32_t* F, int fstride, int64_t naux, int nao, int pblk, int nb,
                         double kappa1, double kappa2_full, double kappa2_last, double occ,
-                        const int32_t* sblk, double* scratch, double* err_bound);
+                        const int32_t* sblk, double* scratch, double* err_bound, int extra = 0);
 
 
 // sliced.hip: the mode with B held as digit planes [planes][naux*nao][ldk]
 // (ldk = nao rounded up to 64, zero padded).
+// packed: A is a packed B (rows P cols + mu), see k_slice_planes.
 hipError_t launch_slice_planes(hipStream_t st, const double* A, int64_t rows, int cols, int ldk,
-                               const int32_t* e, int planes, int8_t* dig);
+                               const int32_t* e, int planes, int8_t* dig, int packed = 0);
 // X (blocked layout) from the B planes and the natural-order C digits; with
 // Dd / d_exp, rowdot[P*nao + mu] = the emulated B row . D row.
 hipError_t launch_x_dig(hipStream_t st, int s, const int8_t* Bd, int64_t bplane, int64_t naux,

@@ -24,7 +24,8 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
                                                 unsigned long long* __restrict__ xmax, int nao,
                                                 int pblk, const double* __restrict__ D,
                                                 double* __restrict__ rowdot,
-                                                const unsigned long long* __restrict__ cmask) {
+                                                const unsigned long long* __restrict__ cmask,
+                                                int packed) {
   constexpr int NT = 16 * NF;
   __shared__ double As[2][64][17];
   __shared__ double Cs[2][16][NT + 1];
@@ -42,7 +43,13 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
   const int lr = t >> 2, lk = (t & 3) * 4;
   const int64_t grow = m0 + lr;
   const bool row_ok = grow < M;
-  const double* brow = B + (row_ok ? grow : 0) * (int64_t)K;
+  // packed B: row (P, mu) of B_P is its stored row (nu <= mu) and column mu
+  // of the rows below (nu > mu); element (mu, nu) at max (max + 1) / 2 + min
+  const int64_t gP = row_ok ? grow / nao : 0;
+  const int gmu = row_ok ? (int)(grow - gP * nao) : 0;
+  const double* bpk = B + gP * ((int64_t)nao * (nao + 1) / 2);
+  const int64_t tri_mu = (int64_t)gmu * (gmu + 1) / 2;
+  const double* brow = B + (row_ok && !packed ? grow : 0) * (int64_t)K;
   const double* drow = D ? D + (row_ok ? grow % nao : 0) * (int64_t)K : nullptr;
   double rd = 0.0;
 
@@ -55,7 +62,12 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int kk = k0 + lk + j;
-      va[j] = (row_ok && kk < K) ? brow[kk] : 0.0;
+      if (packed)
+        va[j] = (row_ok && kk < K)
+                    ? bpk[kk <= gmu ? tri_mu + kk : (int64_t)kk * (kk + 1) / 2 + gmu]
+                    : 0.0;
+      else
+        va[j] = (row_ok && kk < K) ? brow[kk] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
@@ -249,19 +261,19 @@ __global__ void k_xmax_to_exp(const unsigned long long* __restrict__ xmax, int64
 hipError_t launch_x_fp64(hipStream_t st, const double* B, int64_t naux, int nao,
                          const double* C, int nocc, double* X, int xlayout,
                          unsigned long long* xmax, int pblk, const double* D, double* rowdot,
-                         const unsigned long long* cmask) {
+                         const unsigned long long* cmask, int packed) {
   const int64_t M = naux * nao;
   if (M <= 0 || nocc <= 0) return hipSuccess;
   const unsigned gx = (unsigned)((M + 63) / 64);
   if (nocc > 64) {
     hipLaunchKernelGGL((k_x_fp64<6>), dim3(gx, (nocc + 95) / 96), dim3(256), 0, st, B, M, nao, C,
-                       nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
+                       nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask, packed);
   } else if (nocc > 32) {
     hipLaunchKernelGGL((k_x_fp64<4>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X,
-                       xlayout, xmax, nao, pblk, D, rowdot, cmask);
+                       xlayout, xmax, nao, pblk, D, rowdot, cmask, packed);
   } else {
     hipLaunchKernelGGL((k_x_fp64<2>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X,
-                       xlayout, xmax, nao, pblk, D, rowdot, cmask);
+                       xlayout, xmax, nao, pblk, D, rowdot, cmask, packed);
   }
   return hipGetLastError();
 }

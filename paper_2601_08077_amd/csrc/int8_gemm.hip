@@ -86,7 +86,26 @@ __device__ __forceinline__ void digit_rows8(const double* v, int e, uint2* out) 
 // X layout 0: X[row][i]; layout 1 (blocked): X_b rows, element
 // ((b nao + mu) pblk + P - P0) nocc + i.
 // ---------------------------------------------------------------------------
-template <int S, int NF, bool FULLK, int KSUB>
+//
+// Packed B (PK): B_P stored as its lower triangle, row mu >= nu, element
+// (mu, nu) at mu (mu + 1) / 2 + nu (B_P is symmetric).  A tile (P, rows
+// mu0 .. mu0 + 63) reads each 64-wide nu chunk c of its rows in one of three
+// ways: below the tile's diagonal block the rows of the triangle (contiguous,
+// the same lane layout as dense B); the diagonal block element by element
+// (mu >= nu from the row, mu < nu from the mirror); above it the mirrored block,
+// stored as rows nu of the triangle over the tile's mu: then wave w takes the
+// eight nu that lane-in-row w would take and lane l takes tile row l, so every
+// load instruction reads 64 consecutive mu of one stored row (512 B), and the
+// digits are written to LDS row l in the same slots.  Each element is sliced
+// with the exponent of the row it is used for (that of mu in both
+// orientations), so the result is bit-identical to dense B.  The tiles of one
+// P are handed to one XCD together, and tile t visits chunk (s - t) mod n at
+// step s: the two tiles that read one stored block (one directly, one
+// mirrored) read it at the same step, so the second read is served by L2.
+//
+// E extra anti-diagonals (0 or 1): the pairs a + b <= s + 1 + E (a, b <= s)
+// are formed, S + E int32 accumulators per output.
+template <int S, int NF, bool FULLK, int KSUB, bool PK, int E>
 __global__ __launch_bounds__(512) void k_x_int8(
     const double* __restrict__ B, int64_t M, int K, const int32_t* __restrict__ b_exp,
     const int8_t* __restrict__ dC, int ncp, int kp, const int32_t* __restrict__ f_col, int nocc,
@@ -120,16 +139,25 @@ __global__ __launch_bounds__(512) void k_x_int8(
   // Workgroups that run together share the basis-row tile mu0..mu0+63 (and so
   // the same rows of D, which stay in L2) and differ in the aux index P.
   int64_t m0 = (int64_t)blockIdx.x * 64;
-  if (nao % 64 == 0) {
+  int64_t ptile = 0;  // PK: the tile's aux index; mu0 its first row
+  int mu0 = 0;
+  if constexpr (PK) {
+    const int nmt = (nao + 63) >> 6;
+    const int64_t lid = xcd_order(blockIdx.x, gridDim.x);
+    ptile = lid / nmt;
+    mu0 = (int)(lid - ptile * nmt) * 64;
+    m0 = ptile * nao + mu0;
+  } else if (nao % 64 == 0) {
     const int64_t naux = M / nao;
     const int64_t mt = blockIdx.x / naux, P = blockIdx.x - mt * naux;
     m0 = P * nao + mt * 64;
   }
   const int n0 = blockIdx.y * NT;
-  // Rows past M read row 0 (in bounds); their digits and sums are discarded.
+  // Rows past M (PK: past nao) read an in-bounds row; their digits and sums
+  // are discarded.
   const int64_t arow = m0 + lrow;
-  const bool aok = arow < M;
-  const double* brow = B + (aok ? arow : 0) * (int64_t)K + 2 * lm;
+  const bool aok = PK ? mu0 + lrow < nao : arow < M;
+  const double* brow = B + (aok && !PK ? arow : 0) * (int64_t)K + 2 * lm;
   const int e_a = aok ? b_exp[arow] : 0;
   const bool want_rd = D != nullptr;
   const double* drow = (want_rd ? D : B) + (aok ? (arow % nao) : 0) * (int64_t)K + 2 * lm;
@@ -169,9 +197,24 @@ __global__ __launch_bounds__(512) void k_x_int8(
   const __amdgpu_buffer_rsrc_t brsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<double*>(B + m0 * (int64_t)K), (short)0, 64 * K * 8, 0x00020000);
   const __amdgpu_buffer_rsrc_t drsrc = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<double*>((want_rd ? D : B) + (m0 % nao) * (int64_t)K), (short)0, 64 * K * 8,
-      0x00020000);
+      const_cast<double*>((want_rd ? D : B) + (PK ? mu0 : m0 % nao) * (int64_t)K), (short)0,
+      (PK ? min(64, nao - mu0) : 64) * K * 8, 0x00020000);
   const int vbo = (lrow * K + 2 * lm) * 8;
+  // PK: a resource over the stored triangle of B_P, and the per-lane parts of
+  // the offsets (rows clamped to nao - 1: padding rows read a real row).  The
+  // mirrored loader's lane takes tile row l (exponent e_t, LDS row l).
+  const int nao1 = nao - 1;
+  const int mu_c = PK ? min(mu0 + lrow, nao1) : 0;
+  const int muT = mu0 + l, muT_c = PK ? min(muT, nao1) : 0;
+  const __amdgpu_buffer_rsrc_t bprsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(B + (PK ? ptile * ((int64_t)nao * (nao + 1) / 2) : 0)), (short)0,
+      PK ? (int)((int64_t)nao * (nao + 1) / 2 * 8) : 0, 0x00020000);
+  const int voffL = (mu_c * (mu_c + 1) / 2 + 2 * lm) * 8;
+  const int voffT = muT_c * 8;
+  const int vboD = ((PK ? mu_c - mu0 : lrow) * K + 2 * lm) * 8;
+  const int e_t = (PK && muT < nao) ? b_exp[ptile * nao + muT] : 0;
+  int8_t* adstT = &As[0][0][l][swz(l, w >> 1) + (w & 1) * 8];
+  const int wlm = __builtin_amdgcn_readfirstlane(w);  // the mirrored loader's lane-in-row
   if constexpr (NBUF == 2) {
 #pragma unroll
     for (int j = 0; j < CIW; ++j) {
@@ -183,9 +226,10 @@ __global__ __launch_bounds__(512) void k_x_int8(
     }
   }
 
-  i32x4 acc[S][NFW];
+  constexpr int G = S + E;  // anti-diagonals kept
+  i32x4 acc[G][NFW];
 #pragma unroll
-  for (int g = 0; g < S; ++g)
+  for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int f = 0; f < NFW; ++f) acc[g][f] = i32x4{0, 0, 0, 0};
   double rd = 0.0;
@@ -195,14 +239,48 @@ __global__ __launch_bounds__(512) void k_x_int8(
   // element (2 below the diagonal, 1 on it, 0 above; exact weights), chunks
   // past it not at all, and their D rows are not read.
   constexpr bool TRI = NBUF == 2 && FULLK;
-  const int cdiag = TRI ? (int)((m0 % nao) >> 6) : 0;
+  constexpr bool RDTRI = TRI || PK;  // row dots over the chunks up to the diagonal block
+  const int cdiag = PK ? (mu0 >> 6) : (TRI ? (int)((m0 % nao) >> 6) : 0);
 
   double v[NV], dv[NV];
   i32x4 cpre[NBUF == 1 ? CPER : 1];
 #define DFJK_X_LOAD(CC)                                                                    \
   {                                                                                        \
     const int kb0 = (CC) * KC;                                                             \
-    if constexpr (TRI) {                                                                   \
+    if constexpr (PK) {                                                                    \
+      if ((CC) < cdiag) { /* rows of the triangle: 4 loads of 16 B */                      \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                    \
+          const double2 pb = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128( \
+              bprsrc, voffL + 128 * j, kb0 * 8, 0));                                       \
+          v[2 * j] = pb.x;                                                                 \
+          v[2 * j + 1] = pb.y;                                                             \
+        }                                                                                  \
+      } else if ((CC) == cdiag) { /* diagonal block: element by element (columns past */  \
+        /* nao read column nao - 1 and are zeroed when staged, so that no load waits) */   \
+        _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                    \
+          const int nu = kb0 + 16 * (j >> 1) + 2 * lm + (j & 1);                           \
+          const int nuc = min(nu, nao1);                                                   \
+          const int off = nuc <= mu_c ? mu_c * (mu_c + 1) / 2 + nuc : nuc * (nuc + 1) / 2 + mu_c; \
+          v[j] = __builtin_bit_cast(double,                                                \
+              __builtin_amdgcn_raw_buffer_load_b64(bprsrc, off * 8, 0, 0));                \
+        }                                                                                  \
+      } else { /* mirrored block: stored rows nu, 64 consecutive mu per load */            \
+        _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                    \
+          const int nu = kb0 + 16 * (j >> 1) + 2 * wlm + (j & 1);                           \
+          const int nuc = min(nu, nao1);                                                   \
+          v[j] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(          \
+              bprsrc, voffT, nuc * (nuc + 1) / 2 * 8, 0));                                 \
+        }                                                                                  \
+      }                                                                                    \
+      if (want_rd && (CC) <= cdiag) {                                                      \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                    \
+          const double2 pd = __builtin_bit_cast(                                           \
+              double2, __builtin_amdgcn_raw_buffer_load_b128(drsrc, vboD + 128 * j, kb0 * 8, 0)); \
+          dv[2 * j] = pd.x;                                                                \
+          dv[2 * j + 1] = pd.y;                                                            \
+        }                                                                                  \
+      }                                                                                    \
+    } else if constexpr (TRI) {                                                            \
       _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                      \
         const double2 pb = __builtin_bit_cast(                                             \
             double2, __builtin_amdgcn_raw_buffer_load_b128(brsrc, vbo + 128 * j, kb0 * 8, 0)); \
@@ -265,8 +343,14 @@ __global__ __launch_bounds__(512) void k_x_int8(
   // LDS stage BUF (and its B.D row-dot terms into rd / rd_off).
 #define DFJK_X_STAGE(BUF, CC)                                                                   \
   {                                                                                             \
+    if (PK && (nao & 63) && (CC) >= cdiag) { /* PK: columns past nao are zero */                \
+      _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                           \
+        const int nu = (CC) * 64 + 16 * (j >> 1) + 2 * ((CC) == cdiag ? lm : wlm) + (j & 1);    \
+        if (nu >= nao) v[j] = 0.0;                                                              \
+      }                                                                                         \
+    }                                                                                           \
     /* row-dot terms (zeroed after the loop when there is no D) */                              \
-    if constexpr (TRI) {                                                                        \
+    if constexpr (RDTRI) {                                                                      \
       /* below the diagonal block a uniform doubling (v + v == 2 v exactly); at */              \
       /* s <= 3 the single weighted form, which keeps two workgroups per CU */                  \
       if (S >= 4 && (CC) < cdiag) {                                                             \
@@ -281,11 +365,18 @@ __global__ __launch_bounds__(512) void k_x_int8(
     } else {                                                                                    \
       _Pragma("unroll") for (int j = 0; j < NV; ++j) rd = fma(v[j], dv[j], rd);                 \
     }                                                                                           \
-    _Pragma("unroll") for (int sub = 0; sub < KSUB; ++sub) {                                    \
+    if (PK && (CC) > cdiag) { /* mirrored block: this lane's values are tile row l's */         \
       uint2 rows[S];                                                                            \
-      digit_rows8<S>(&v[8 * sub], e_a, rows);                                                   \
+      digit_rows8<S>(v, e_t, rows);                                                             \
       _Pragma("unroll") for (int a = 0; a < S; ++a)                                             \
-        *reinterpret_cast<uint2*>(adst + ((BUF) * S + a) * 64 * ROW + sub * 64) = rows[a];      \
+        *reinterpret_cast<uint2*>(adstT + ((BUF) * S + a) * 64 * ROW) = rows[a];                \
+    } else {                                                                                    \
+      _Pragma("unroll") for (int sub = 0; sub < KSUB; ++sub) {                                  \
+        uint2 rows[S];                                                                          \
+        digit_rows8<S>(&v[8 * sub], e_a, rows);                                                 \
+        _Pragma("unroll") for (int a = 0; a < S; ++a)                                           \
+          *reinterpret_cast<uint2*>(adst + ((BUF) * S + a) * 64 * ROW + sub * 64) = rows[a];    \
+      }                                                                                         \
     }                                                                                           \
     if constexpr (NBUF == 1) {                                                                  \
       _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                        \
@@ -306,14 +397,22 @@ __global__ __launch_bounds__(512) void k_x_int8(
       _Pragma("unroll") for (int b = 0; b < S; ++b) bf[b] =                                     \
           *reinterpret_cast<const i32x4*>(&DFJK_CSB(BUF)[b * NT + col][sub * 64 + swz(col, q)]); \
       _Pragma("unroll") for (int a = 0; a < S; ++a)                                             \
-        _Pragma("unroll") for (int b = 0; b < S - a; ++b) acc[a + b][f] =                       \
+        _Pragma("unroll") for (int b = 0; b < (S - a + E < S ? S - a + E : S); ++b)             \
+          acc[a + b][f] =                                                                       \
             __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a + b][f], 0, 0, 0);        \
     }                                                                                           \
   }
 
-  int c = cmask ? first_bit(live) : (nch > 0 ? 0 : -1);
+  // PK: tile mt visits chunk (step - mt) mod nch at each step (all nch chunks,
+  // wrapping around); otherwise ascending (screened: the live chunks only).
+  const int cfirst = PK ? (nch - cdiag % nch) % nch : 0;
+  const int clast = PK ? (cfirst + nch - 1) % nch : nch - 1;
+  int c = cmask ? first_bit(live) : (nch > 0 ? cfirst : -1);
   auto next_of = [&](int cc) {
-    return cc < 0 ? -1 : (cmask ? next_bit(live, cc) : (cc + 1 < nch ? cc + 1 : -1));
+    if (cc < 0) return -1;
+    if (cmask) return next_bit(live, cc);
+    if (PK) return cc == clast ? -1 : (cc + 1 == nch ? 0 : cc + 1);
+    return cc + 1 < nch ? cc + 1 : -1;
   };
   if constexpr (NBUF == 2) {
     // stage c into LDS 0, prefetch the next chunk into registers; then per
@@ -348,7 +447,15 @@ __global__ __launch_bounds__(512) void k_x_int8(
     if (cnn >= 0) DFJK_X_LOAD(cnn)                                                              \
     __builtin_amdgcn_sched_barrier(0);                                                          \
     DFJK_X_MMA(BB)                                                                              \
-    if (FULLK && cnn >= 0 && want_rd && cnn <= cdiag)                                           \
+    /* PK: chunk cnn's loads are 4 (rows), 8 (diagonal, mirrored) B loads, plus */              \
+    /* 4 D loads up to the diagonal block */                                                    \
+    if (PK && cnn >= 0 && cnn == cdiag && want_rd)                                              \
+      asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");                \
+    else if (PK && cnn >= 0 && (cnn == cdiag || cnn > cdiag || want_rd))                       \
+      asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");                 \
+    else if (PK && cnn >= 0)                                                                    \
+      asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");                 \
+    else if (FULLK && cnn >= 0 && want_rd && cnn <= cdiag)                                      \
       asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");                 \
     else if (FULLK && cnn >= 0)                                                                 \
       asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");                 \
@@ -394,9 +501,9 @@ __global__ __launch_bounds__(512) void k_x_int8(
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int64_t row = m0 + wrow * 16 + q * 4 + r;
-    const bool vr = row < M;
+    const bool vr = PK ? mu0 + wrow * 16 + q * 4 + r < nao : row < M;
     const int er = vr ? b_exp[row] : 0;
-    const int64_t P = vr ? row / nao : 0;
+    const int64_t P = PK ? ptile : (vr ? row / nao : 0);
     const int mu = (int)(row - P * nao);
     const int64_t b = P / pblk;
     double* xrow = xlayout ? X + (((b * nao + mu) * pblk + (P - b * pblk)) * (int64_t)nocc)
@@ -409,12 +516,12 @@ __global__ __launch_bounds__(512) void k_x_int8(
         const int base = er + f_col[col] + 4;
         double z = 0.0;
 #pragma unroll
-        for (int g = S + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][f][r], base - 8 * g);
+        for (int g = G + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][f][r], base - 8 * g);
         xrow[col] = z;
         rmax = fmax(rmax, fabs(z));
         if (dbg) {  // test export: the int32 anti-diagonal sums of this tile
 #pragma unroll
-          for (int g = 0; g < S; ++g) dbg[((int64_t)g * M + row) * nocc + col] = acc[g][f][r];
+          for (int g = 0; g < G; ++g) dbg[((int64_t)g * M + row) * nocc + col] = acc[g][f][r];
         }
       }
     }
@@ -504,7 +611,7 @@ __device__ __forceinline__ void lower_tile(int idx, int& t1, int& t2) {
 // 16 rows per wave instruction), while the MFMAs run on the other stage; one
 // barrier per step.
 // ---------------------------------------------------------------------------
-template <int S, bool DBG>
+template <int S, bool DBG, int E>
 __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
                                                 const int32_t* __restrict__ F, int nb, int nao,
                                                 int nao_pad, int kbp, int groups,
@@ -561,9 +668,10 @@ __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) kacc[i][r] = 0.0;
-  i32x4 acc[S][2];
+  constexpr int G = S + E;  // anti-diagonals kept (E extra ones)
+  i32x4 acc[G][2];
 #pragma unroll
-  for (int g = 0; g < S; ++g)
+  for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int i = 0; i < 2; ++i) acc[g][i] = i32x4{0, 0, 0, 0};
 
@@ -583,7 +691,7 @@ __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
 #pragma unroll
       for (int a = 0; a < S; ++a)
 #pragma unroll
-        for (int bb = 0; bb < S - a; ++bb)
+        for (int bb = 0; bb < (S - a + E < S ? S - a + E : S); ++bb)
           acc[a + bb][i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[bb], acc[a + bb][i], 0, 0, 0);
     }
   };
@@ -600,7 +708,7 @@ __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
           const int mu = t1 * 64 + wr + i * 16 + q * 4 + r;
           if (mu < nao && nu < nao) {
 #pragma unroll
-            for (int g = 0; g < S; ++g)
+            for (int g = 0; g < G; ++g)
               dbg[(((int64_t)g * nb + b) * nao + mu) * nao + nu] = acc[g][i][r];
           }
         }
@@ -612,11 +720,11 @@ __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
         const int base = Fb[t1 * 64 + wr + i * 16 + q * 4 + r] + fn + 4;
         double z = 0.0;
 #pragma unroll
-        for (int g = S + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][i][r], base - 8 * g);
+        for (int g = G + 1; g >= 2; --g) z += ldexp((double)acc[g - 2][i][r], base - 8 * g);
         kacc[i][r] += z;
       }
 #pragma unroll
-    for (int g = 0; g < S; ++g)
+    for (int g = 0; g < G; ++g)
 #pragma unroll
       for (int i = 0; i < 2; ++i) acc[g][i] = i32x4{0, 0, 0, 0};
   };
@@ -710,21 +818,26 @@ __global__ __launch_bounds__(64) void k_debug_pairs(const int8_t* __restrict__ A
   }
 }
 
-template <int S, bool FULLK, int KSUB>
+template <int S, bool FULLK, int KSUB, bool PK = false, int E = 0>
 hipError_t launch_x_sk(hipStream_t st, const double* B, int64_t M, int nao, const int32_t* b_exp,
                        const int8_t* dC, int ncp, int kp, const int32_t* f_col, int nocc,
                        double* X, int xlayout, unsigned long long* xmax, int pblk, const double* D,
                        double* rowdot, const unsigned long long* cmask, int32_t* dbg) {
-  const unsigned gx = (unsigned)((M + 63) / 64);
+  // PK: one tile per (P, 64 rows of B_P); else 64 consecutive rows of the
+  // stacked (P, mu) rows
+  const unsigned gx = PK ? (unsigned)(M / nao * ((nao + 63) / 64)) : (unsigned)((M + 63) / 64);
   if (ncp % 96 == 0) {
-    hipLaunchKernelGGL((k_x_int8<S, 6, FULLK, KSUB>), dim3(gx, ncp / 96), dim3(512), 0, st, B, M,
-                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask, dbg);
+    hipLaunchKernelGGL((k_x_int8<S, 6, FULLK, KSUB, PK, E>), dim3(gx, ncp / 96), dim3(512), 0, st, B,
+                       M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D,
+                       rowdot, cmask, dbg);
   } else if (ncp % 64 == 0) {
-    hipLaunchKernelGGL((k_x_int8<S, 4, FULLK, KSUB>), dim3(gx, ncp / 64), dim3(512), 0, st, B, M,
-                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask, dbg);
+    hipLaunchKernelGGL((k_x_int8<S, 4, FULLK, KSUB, PK, E>), dim3(gx, ncp / 64), dim3(512), 0, st, B,
+                       M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D,
+                       rowdot, cmask, dbg);
   } else {
-    hipLaunchKernelGGL((k_x_int8<S, 2, FULLK, KSUB>), dim3(gx, ncp / 32), dim3(512), 0, st, B, M,
-                       nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask, dbg);
+    hipLaunchKernelGGL((k_x_int8<S, 2, FULLK, KSUB, PK, E>), dim3(gx, ncp / 32), dim3(512), 0, st, B,
+                       M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D,
+                       rowdot, cmask, dbg);
   }
   return hipGetLastError();
 }
@@ -736,7 +849,21 @@ template <int S>
 hipError_t launch_x_s(hipStream_t st, const double* B, int64_t M, int nao, const int32_t* b_exp,
                       const int8_t* dC, int ncp, int kp, const int32_t* f_col, int nocc,
                       double* X, int xlayout, unsigned long long* xmax, int pblk, const double* D,
-                      double* rowdot, const unsigned long long* cmask, int ksub, int32_t* dbg) {
+                      double* rowdot, const unsigned long long* cmask, int ksub, int32_t* dbg,
+                      int packed, int extra) {
+  if (S > 1 && extra) {  // one extra anti-diagonal: 64-wide chunks
+    if (packed)
+      return launch_x_sk<S, true, 1, true, 1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X,
+                                              xlayout, xmax, pblk, D, rowdot, nullptr, dbg);
+    if (nao % 64 == 0)
+      return launch_x_sk<S, true, 1, false, 1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X,
+                                               xlayout, xmax, pblk, D, rowdot, cmask, dbg);
+    return launch_x_sk<S, false, 1, false, 1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X,
+                                              xlayout, xmax, pblk, D, rowdot, cmask, dbg);
+  }
+  if (packed)  // 64-wide chunks; no screening masks
+    return launch_x_sk<S, true, 1, true>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout,
+                                         xmax, pblk, D, rowdot, nullptr, dbg);
   if (S <= 5 && nao % 128 == 0 && ksub == 2)
     return launch_x_sk<S, true, (S <= 5 ? 2 : 1)>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X,
                                                    xlayout, xmax, pblk, D, rowdot, cmask, dbg);
@@ -753,18 +880,19 @@ hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, i
                          const int32_t* b_exp, const int8_t* dC, int ncp, int kp,
                          const int32_t* f_col, int nocc, double* X, int xlayout,
                          unsigned long long* xmax, int pblk, const double* D, double* rowdot,
-                         const unsigned long long* cmask, int ksub, int32_t* dbg) {
+                         const unsigned long long* cmask, int ksub, int32_t* dbg, int packed,
+                         int extra) {
   const int64_t M = naux * nao;
   if (M <= 0 || nocc <= 0) return hipSuccess;
   switch (s) {
-    case 1: return launch_x_s<1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
-    case 2: return launch_x_s<2>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
-    case 3: return launch_x_s<3>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
-    case 4: return launch_x_s<4>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
-    case 5: return launch_x_s<5>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
-    case 6: return launch_x_s<6>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
-    case 7: return launch_x_s<7>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
-    case 8: return launch_x_s<8>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg);
+    case 1: return launch_x_s<1>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg, packed, extra);
+    case 2: return launch_x_s<2>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg, packed, extra);
+    case 3: return launch_x_s<3>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg, packed, extra);
+    case 4: return launch_x_s<4>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg, packed, extra);
+    case 5: return launch_x_s<5>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg, packed, extra);
+    case 6: return launch_x_s<6>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg, packed, extra);
+    case 7: return launch_x_s<7>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg, packed, extra);
+    case 8: return launch_x_s<8>(st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, pblk, D, rowdot, cmask, ksub, dbg, packed, extra);
     default: return hipErrorInvalidValue;
   }
 }
@@ -802,7 +930,7 @@ int k_int8_resident(int s) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
 #define DFJK_KOCC(SS) \
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_k_int8<SS, false>), 512, 0)
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_k_int8<SS, false, 0>), 512, 0)
   switch (s) {
     case 1: DFJK_KOCC(1); break;
     case 2: DFJK_KOCC(2); break;
@@ -821,15 +949,22 @@ int k_int8_resident(int s) {
 }
 
 hipError_t launch_k_int8(hipStream_t st, int s, const int8_t* Xd, const int32_t* F, int nb,
-                         int nao, int nao_pad, int kbp, int groups, double* Kp, int32_t* dbg) {
+                         int nao, int nao_pad, int kbp, int groups, double* Kp, int32_t* dbg,
+                         int extra) {
   const int nt = nao_pad / 64;
   const dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)groups);
-#define DFJK_K(SS) \
-  if (dbg)                                                                                     \
-    hipLaunchKernelGGL((k_k_int8<SS, true>), grid, dim3(512), 0, st, Xd, F, nb, nao, nao_pad, kbp, \
-                       groups, Kp, dbg);                                                        \
-  else                                                                                         \
-    hipLaunchKernelGGL((k_k_int8<SS, false>), grid, dim3(512), 0, st, Xd, F, nb, nao, nao_pad,  \
+#define DFJK_K(SS)                                                                            \
+  if (SS > 1 && extra && dbg)                                                                 \
+    hipLaunchKernelGGL((k_k_int8<SS, true, (SS > 1 ? 1 : 0)>), grid, dim3(512), 0, st, Xd, F, nb, \
+                       nao, nao_pad, kbp, groups, Kp, dbg);                                   \
+  else if (SS > 1 && extra)                                                                   \
+    hipLaunchKernelGGL((k_k_int8<SS, false, (SS > 1 ? 1 : 0)>), grid, dim3(512), 0, st, Xd, F, nb, \
+                       nao, nao_pad, kbp, groups, Kp, nullptr);                               \
+  else if (dbg)                                                                               \
+    hipLaunchKernelGGL((k_k_int8<SS, true, 0>), grid, dim3(512), 0, st, Xd, F, nb, nao, nao_pad, \
+                       kbp, groups, Kp, dbg);                                                 \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_k_int8<SS, false, 0>), grid, dim3(512), 0, st, Xd, F, nb, nao, nao_pad, \
                        kbp, groups, Kp, nullptr)
   switch (s) {
     case 1: DFJK_K(1); break;

@@ -47,11 +47,14 @@ __global__ __launch_bounds__(256) void k_rho(const double* __restrict__ B, int64
 // nu <= mu.  Workgroup w takes rows w and nao - 1 - w, nao + 1 elements in
 // all, so every workgroup streams the same number of bytes; thread t owns
 // elements t, t + 256, ... of the two rows, concatenated.
+// Packed B (packed != 0): B_P is its lower triangle by rows, element (mu, nu)
+// at mu (mu + 1) / 2 + nu, so the two rows of a workgroup are contiguous.
 template <int EPT>
 __global__ __launch_bounds__(256) void k_j_tri(const double* __restrict__ B, int64_t naux, int nao,
                                                const double* __restrict__ rho, int jsplit,
                                                double* __restrict__ out, int mirror,
-                                               const uint8_t* __restrict__ smask, int blk) {
+                                               const uint8_t* __restrict__ smask, int blk,
+                                               int packed) {
   const int w = blockIdx.x;
   const int mu0 = w, mu1 = nao - 1 - w;
   const int n0 = mu0 + 1;
@@ -59,8 +62,9 @@ __global__ __launch_bounds__(256) void k_j_tri(const double* __restrict__ B, int
   const int split = blockIdx.y;
   const int64_t p_lo = (int64_t)split * naux / jsplit, p_hi = (int64_t)(split + 1) * naux / jsplit;
   const int64_t nn = (int64_t)nao * nao;
+  const int64_t pstride = packed ? (int64_t)nao * (nao + 1) / 2 : nn;  // per aux index
   for (int base = 0; base < ntot; base += 256 * EPT) {
-    int64_t off[EPT];
+    int64_t off[EPT], boff[EPT];
     bool ok[EPT], rd[EPT];
     const int nblk = (nao + blk - 1) / blk;
 #pragma unroll
@@ -70,6 +74,7 @@ __global__ __launch_bounds__(256) void k_j_tri(const double* __restrict__ B, int
       const int mu = idx < n0 ? mu0 : mu1;
       const int nu = idx < n0 ? idx : idx - n0;
       off[j] = ok[j] ? (int64_t)mu * nao + nu : 0;
+      boff[j] = ok[j] ? (packed ? (int64_t)mu * (mu + 1) / 2 + nu : off[j]) : 0;
       // a dropped shell block of the screened B is zero: its sum is 0
       rd[j] = ok[j] && (!smask || smask[(mu / blk) * nblk + nu / blk]);
     }
@@ -83,7 +88,7 @@ __global__ __launch_bounds__(256) void k_j_tri(const double* __restrict__ B, int
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) bv[u][j] = rd[j] ? B[(P + u) * nn + off[j]] : 0.0;
+        for (int j = 0; j < EPT; ++j) bv[u][j] = rd[j] ? B[(P + u) * pstride + boff[j]] : 0.0;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const double r = rho[P + u];
@@ -94,10 +99,10 @@ __global__ __launch_bounds__(256) void k_j_tri(const double* __restrict__ B, int
     }
     for (; P < p_hi; ++P) {
       const double r = rho[P];
-      const double* bp = B + P * nn;
+      const double* bp = B + P * pstride;
 #pragma unroll
       for (int j = 0; j < EPT; ++j)
-        if (rd[j]) a[j] = fma(r, bp[off[j]], a[j]);
+        if (rd[j]) a[j] = fma(r, bp[boff[j]], a[j]);
     }
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
@@ -140,6 +145,33 @@ __global__ void k_k_reduce(const double* __restrict__ Kp, int groups, int nao, d
     K[e] = v;
     K[(int64_t)nu * nao + mu] = v;
   }
+}
+
+// Fock matrix of the closed-shell SCF around the build (the paper's Sec. 4.3
+// iterations): F = h + J - K / 2 elementwise ((h + J) first), and the partial
+// sums of tr(D h) over fixed slices (256 workgroups, grid-stride), summed in
+// order by k_sum_parts.
+__global__ __launch_bounds__(256) void k_fock(const double* __restrict__ h,
+                                              const double* __restrict__ J,
+                                              const double* __restrict__ K,
+                                              const double* __restrict__ D, int64_t nn,
+                                              double* __restrict__ F, double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nn; i += (int64_t)gridDim.x * 256) {
+    const double hv = h[i];
+    F[i] = (hv + J[i]) - 0.5 * K[i];
+    acc = fma(D[i], hv, acc);
+  }
+  const double r = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int n, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double v = 0.0;
+  for (int i = 0; i < n; ++i) v += part[i];
+  *out = v;
 }
 
 // Energies in two deterministic passes: 256 workgroups reduce fixed slices of
@@ -196,7 +228,8 @@ __global__ __launch_bounds__(256) void k_rho_reduce(const double* __restrict__ r
 __global__ void k_bound_prep(const int32_t* __restrict__ b_exp, const int32_t* __restrict__ f_col,
                              int nocc, const int32_t* __restrict__ F, int fstride, int64_t naux,
                              int nao, int pblk, int nb, double kappa1,
-                             const int32_t* __restrict__ sblk, double* __restrict__ scratch) {
+                             const int32_t* __restrict__ sblk, double* __restrict__ scratch,
+                             int extra) {
   double fsum = 0.0, fmx = 0.0;
   for (int i = 0; i < nocc; ++i) {
     const double v = ldexp(1.0, f_col[i]);
@@ -209,7 +242,7 @@ __global__ void k_bound_prep(const int32_t* __restrict__ b_exp, const int32_t* _
     const int b = (int)(idx / nao), mu = (int)(idx - (int64_t)b * nao);
     const int64_t p0 = (int64_t)b * pblk;
     const int64_t p1 = p0 + pblk < naux ? p0 + pblk : naux;
-    const double k1 = sblk ? kappa_of(sblk[b], nao) : kappa1;
+    const double k1 = sblk ? kappa_of(sblk[b], nao, extra) : kappa1;
     double se = 0.0, me = 0.0;
     // eight independent exponent loads in flight per step (the sum order is
     // unchanged: P ascending)
@@ -243,7 +276,7 @@ __global__ __launch_bounds__(256) void k_bound(const double* __restrict__ scratc
                                                int64_t naux, int pblk, int nocc,
                                                double kappa2_full, double kappa2_last, double occ,
                                                int occ_pow2, const int32_t* __restrict__ sblk,
-                                               double* __restrict__ err_bound) {
+                                               double* __restrict__ err_bound, int extra) {
   // lane: one nu of the 256-wide column chunk blockIdx.x; the workgroup's
   // KB_ROWS rows mu (blockIdx.y) are the same for every lane, so each lane reads
   // its nu terms once per block and the mu terms are uniform loads
@@ -262,7 +295,7 @@ __global__ __launch_bounds__(256) void k_bound(const double* __restrict__ scratc
     const double sn0 = sn[0], sn2 = sn[2];
     const int64_t p0 = (int64_t)b * pblk;
     const int64_t kb = ((p0 + pblk < naux ? p0 + pblk : naux) - p0) * nocc;
-    const double k2 = sblk ? kappa_of(sblk[b], kb) : (b == nb - 1 ? kappa2_last : kappa2_full);
+    const double k2 = sblk ? kappa_of(sblk[b], kb, extra) : (b == nb - 1 ? kappa2_last : kappa2_full);
 #pragma unroll
     for (int m = 0; m < KB_ROWS; ++m) {
       const int mu = mu0 + m < nao ? mu0 + m : nao - 1;
@@ -300,17 +333,27 @@ hipError_t launch_rho(hipStream_t st, const double* B, int64_t naux, int nao, co
 }
 
 hipError_t launch_j(hipStream_t st, const double* B, int64_t naux, int nao, const double* rho,
-                    int jsplit, double* Jp, double* J, const uint8_t* smask, int blk) {
+                    int jsplit, double* Jp, double* J, const uint8_t* smask, int blk, int packed) {
   const int64_t nn = (int64_t)nao * nao;
   const dim3 grid((unsigned)((nao + 1) / 2), (unsigned)jsplit);
   if (jsplit <= 1) {
-    hipLaunchKernelGGL((k_j_tri<4>), grid, dim3(256), 0, st, B, naux, nao, rho, 1, J, 1, smask, blk);
+    hipLaunchKernelGGL((k_j_tri<4>), grid, dim3(256), 0, st, B, naux, nao, rho, 1, J, 1, smask, blk,
+                       packed);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_j_tri<4>), grid, dim3(256), 0, st, B, naux, nao, rho, jsplit, Jp, 0, smask, blk);
+  hipLaunchKernelGGL((k_j_tri<4>), grid, dim3(256), 0, st, B, naux, nao, rho, jsplit, Jp, 0, smask,
+                     blk, packed);
   int64_t g = (nn + 255) / 256;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)g), dim3(256), 0, st, Jp, jsplit, nao, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_fock(hipStream_t st, const double* h, const double* J, const double* K,
+                       const double* D, int64_t nao, double* F, double* scratch, double* e_one) {
+  const int64_t nn = nao * nao;
+  hipLaunchKernelGGL(k_fock, dim3(256), dim3(256), 0, st, h, J, K, D, nn, F, scratch);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, scratch, 256, e_one);
   return hipGetLastError();
 }
 
@@ -342,12 +385,12 @@ hipError_t launch_rho_reduce(hipStream_t st, const double* rowdot, int64_t naux,
 hipError_t launch_bound(hipStream_t st, const int32_t* b_exp, const int32_t* f_col, int nocc,
                         const int32_t* F, int fstride, int64_t naux, int nao, int pblk, int nb,
                         double kappa1, double kappa2_full, double kappa2_last, double occ,
-                        const int32_t* sblk, double* scratch, double* err_bound) {
+                        const int32_t* sblk, double* scratch, double* err_bound, int extra) {
   const int64_t n = (int64_t)nb * nao;
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_bound_prep, dim3((unsigned)g), dim3(256), 0, st, b_exp, f_col, nocc, F,
-                     fstride, naux, nao, pblk, nb, kappa1, sblk, scratch);
+                     fstride, naux, nao, pblk, nb, kappa1, sblk, scratch, extra);
   hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(1), 0, st, err_bound);
   int occ_pow2 = 0;
   {
@@ -358,7 +401,7 @@ hipError_t launch_bound(hipStream_t st, const int32_t* b_exp, const int32_t* f_c
   // 256 columns nu by 8 rows mu per workgroup (the row count is k_bound's)
   const dim3 g2((unsigned)((nao + 255) / 256), (unsigned)((nao + 7) / 8));
   hipLaunchKernelGGL(k_bound, g2, dim3(256), 0, st, scratch, nao, nb, naux, pblk,
-                     nocc, kappa2_full, kappa2_last, occ, occ_pow2, sblk, err_bound);
+                     nocc, kappa2_full, kappa2_last, occ, occ_pow2, sblk, err_bound, extra);
   return hipGetLastError();
 }
 

@@ -23,11 +23,13 @@ __device__ __forceinline__ uint32_t pack4(uint64_t w0, uint64_t w1, uint64_t w2,
 }
 
 // dig[a][r][ldk] = digit a + 1 of A[r][c] (row exponent e[r]); columns c >= cols
-// are zero.  One thread per 16 output bytes of a row.
+// are zero.  One thread per 16 output bytes of a row.  packed != 0: A is a
+// packed B (rows r = P cols + mu of B_P; B_P stored as its lower triangle by
+// rows, element (mu, c) at max (max + 1) / 2 + min), read element by element.
 __global__ __launch_bounds__(256) void k_slice_planes(const double* __restrict__ A, int64_t rows,
                                                       int cols, int ldk,
                                                       const int32_t* __restrict__ e, int planes,
-                                                      int8_t* __restrict__ dig) {
+                                                      int8_t* __restrict__ dig, int packed) {
   const int nc = ldk / 16;
   const int64_t total = rows * nc;
   const int64_t plane = rows * (int64_t)ldk;
@@ -38,7 +40,17 @@ __global__ __launch_bounds__(256) void k_slice_planes(const double* __restrict__
     const double* src = A + r * cols + c0;
     const int er = e[r];
     uint64_t wd[16];
-    if (c0 + 16 <= cols && (cols & 1) == 0) {
+    if (packed) {
+      const int64_t P = r / cols;
+      const int mu = (int)(r - P * cols);
+      const double* bp = A + P * ((int64_t)cols * (cols + 1) / 2);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int c = c0 + j;
+        const int64_t o = c <= mu ? (int64_t)mu * (mu + 1) / 2 + c : (int64_t)c * (c + 1) / 2 + mu;
+        wd[j] = c < cols ? digit_word(bp[o], er) : 0ull;
+      }
+    } else if (c0 + 16 <= cols && (cols & 1) == 0) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const double2 p = *reinterpret_cast<const double2*>(src + 2 * j);
@@ -531,10 +543,10 @@ hipError_t x_dig_s(hipStream_t st, const int8_t* Bd, int64_t bplane, int64_t M, 
 }  // namespace
 
 hipError_t launch_slice_planes(hipStream_t st, const double* A, int64_t rows, int cols, int ldk,
-                               const int32_t* e, int planes, int8_t* dig) {
+                               const int32_t* e, int planes, int8_t* dig, int packed) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_slice_planes, dim3(cap(rows * (ldk / 16))), dim3(256), 0, st, A, rows, cols,
-                     ldk, e, planes, dig);
+                     ldk, e, planes, dig, packed);
   return hipGetLastError();
 }
 

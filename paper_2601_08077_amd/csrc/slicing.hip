@@ -28,6 +28,56 @@ __global__ __launch_bounds__(256) void k_row_exp(const double* __restrict__ A, i
   }
 }
 
+// Row exponents of packed B (B_P stored as its lower triangle by rows, element
+// (mu, nu), mu >= nu, at mu (mu + 1) / 2 + nu): the maximum of row mu of B_P
+// is the maximum over its stored row (nu <= mu) and over column mu of the rows
+// below (nu > mu).  Workgroup (64 rows, P): waves take rows for the first part
+// (lanes along the row), lanes take the 64 rows for the second (each load
+// instruction reads 64 consecutive mu of one stored row nu).
+__global__ __launch_bounds__(256) void k_row_exp_packed(const double* __restrict__ B, int nao,
+                                                        int32_t* __restrict__ e, int* status) {
+  __shared__ double rowm[64];
+  __shared__ double part[4][64];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int mu0 = blockIdx.x * 64;
+  const int64_t P = blockIdx.y;
+  const double* bp = B + P * ((int64_t)nao * (nao + 1) / 2);
+  bool bad = false;
+  for (int r = w; r < 64; r += 4) {
+    const int mu = mu0 + r;
+    double m = 0.0;
+    if (mu < nao) {
+      const double* row = bp + (int64_t)mu * (mu + 1) / 2;
+      for (int nu = l; nu <= mu; nu += kWave) {
+        const double v = row[nu];
+        bad |= !isfinite(v);
+        m = fmax(m, fabs(v));
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (l == 0) rowm[r] = m;
+  }
+  const int mu = mu0 + l;
+  double m2 = 0.0;
+  if (mu < nao) {
+    for (int nu = mu0 + 1 + w; nu < nao; nu += 4) {
+      if (nu > mu) {
+        const double v = bp[(int64_t)nu * (nu + 1) / 2 + mu];
+        bad |= !isfinite(v);
+        m2 = fmax(m2, fabs(v));
+      }
+    }
+  }
+  part[w][l] = m2;
+  if (__any(bad) && l == 0) atomicOr(status, kStatusNonFinite);
+  __syncthreads();
+  if (w == 0 && mu < nao) {
+    const double m = fmax(fmax(rowm[l], part[0][l]), fmax(fmax(part[1][l], part[2][l]), part[3][l]));
+    e[P * nao + mu] = exp_of_max(m);
+  }
+}
+
 // f[i] = exponent of max_nu |C[nu][i]| (the columns of C are the rows of the
 // right operand of Eq. 5 over its contraction index nu): one wavefront per column.
 __global__ __launch_bounds__(256) void k_col_exp(const double* __restrict__ C, int64_t nao,
@@ -111,6 +161,14 @@ hipError_t launch_row_exp(hipStream_t st, const double* A, int64_t rows, int64_t
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_row_exp, dim3(grid_for(rows * 64, 256)), dim3(256), 0, st, A, rows,
                      cols, lda, e, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_exp_packed(hipStream_t st, const double* B, int64_t naux, int nao,
+                                 int32_t* e, int* status) {
+  if (naux <= 0 || nao <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((nao + 63) / 64), (unsigned)naux);
+  hipLaunchKernelGGL(k_row_exp_packed, grid, dim3(256), 0, st, B, nao, e, status);
   return hipGetLastError();
 }
 
