@@ -65,8 +65,8 @@ enum df_status {
  *   DF_PACKED [naux][nao (nao + 1) / 2], the lower triangle of each B_P by
  *             rows: element (mu, nu), mu >= nu, at mu (mu + 1) / 2 + nu (the
  *             stored form of Sec. 3.3; half the bytes).  nao <= 16383.  Taken
- *             by df_b_exponents, df_build_x, df_build_jk, df_prepare_b and
- *             df_debug_build_i32; results are bit-identical to
+ *             by df_b_exponents, df_build_x, df_build_jk, df_build_jk_noalloc,
+ *             df_prepare_b and df_debug_build_i32; results are bit-identical to
  *             the same build on the dense tensor, except rho (and so J and E_J),
  *             which may differ in FP64 rounding order.  Screening, the
  *             autotuner, the batched build and df_spot_check take DF_DENSE. */
@@ -177,6 +177,23 @@ int df_build_x(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t n
 int df_build_jk(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t nao,
                 const int32_t* b_exp, const double* C, int64_t nocc, double occ,
                 const double* D, double* J, double* K, double* energies, double* err_bound);
+
+/* df_build_jk without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Arguments, results and errors are those of
+ * df_build_jk; the workspace is a static device array of 64 MiB that every
+ * device holds from the load of the library until the process ends (its
+ * address is looked up by df_create).  Shapes whose df_workspace_size exceeds
+ * 64 MiB return DF_EWORKSPACE (about nao <= 160 with naux = 4 nao and nocc =
+ * nao / 8; nao 96, naux 384, nocc 16 needs 15 MiB); the call
+ * allocates nothing and does not touch the context's own workspace.  All
+ * calls on one device share that array, which keeps the last call's contents:
+ * calls that overlap in time on one device (several streams or contexts)
+ * race; calls ordered on one stream do not. */
+int df_build_jk_noalloc(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t nao,
+                        const int32_t* b_exp, const double* C, int64_t nocc, double occ,
+                        const double* D, double* J, double* K, double* energies,
+                        double* err_bound);
 
 /* Sliced mode, step 1 (once per B; Sec. 3.2 splitting applied to B itself):
  * b_exp[P*nao + mu] as in df_b_exponents and the first `planes` (1..8) digit

@@ -48,6 +48,9 @@ SIGNATURES = {
                           _c_void_p]),
     "df_build_jk": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _c_void_p, _c_void_p, _i64,
                            ctypes.c_double, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "df_build_jk_noalloc": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _c_void_p, _c_void_p,
+                                   _i64, ctypes.c_double, _c_void_p, _c_void_p, _c_void_p,
+                                   _c_void_p, _c_void_p]),
     "df_prepare_b_size": (_int, [_i64, _i64, _int, ctypes.POINTER(ctypes.c_size_t)]),
     "df_prepare_b": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _int, _c_void_p, _c_void_p]),
     "df_build_jk_sliced": (_int, [_c_void_p, _c_void_p, _int, _c_void_p, _i64, _i64, _c_void_p,
@@ -256,6 +259,15 @@ class Context:
         self._check(self.lib.df_build_jk(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp), _ptr(C),
                                          C.shape[1], float(occ), _ptr(D), _ptr(J), _ptr(K),
                                          _ptr(energies), _ptr(err_bound)), "df_build_jk")
+
+    def df_build_jk_noalloc(self, B, b_exp, C, occ, D, J, K, energies, err_bound,
+                            layout=DF_DENSE, naux=None, nao=None):
+        """df_build_jk on the library's static 64 MiB workspace (no allocation)."""
+        naux, nao = _shape(B, layout, naux, nao)
+        self._check(self.lib.df_build_jk_noalloc(self.h, _ptr(B), layout, naux, nao, _ptr(b_exp),
+                                                 _ptr(C), C.shape[1], float(occ), _ptr(D),
+                                                 _ptr(J), _ptr(K), _ptr(energies),
+                                                 _ptr(err_bound)), "df_build_jk_noalloc")
 
     def df_prepare_b(self, B, planes, b_exp, b_dig, layout=DF_DENSE, naux=None, nao=None):
         """b_exp [naux*nao] int32, b_dig [planes][naux*nao][ldk] int8 (ldk = nao

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -22,6 +23,7 @@ struct df_ctx {
   int x_ksub_req = 0;  // X chunk depth asked for (0 = autotuned or default)
   int extra = 0;       // anti-diagonals of digit pairs kept beyond a + b = s + 1
   int ncu = 256;  // compute units of the context's device
+  int dev = -1;   // device current at df_create
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int* status = nullptr;  // device word owned by the context
@@ -52,6 +54,17 @@ struct df_ctx {
 };
 
 constexpr size_t kAuxBytes = (size_t)8 << 20;
+
+// Workspace of df_build_jk_noalloc: one static array per device, held from
+// the load of the library until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address that df_create looks up once per
+// device with that device current.
+constexpr size_t kStaticWsBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kStaticWsBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
 
 namespace {
 
@@ -433,10 +446,26 @@ int df_create(df_ctx** ctx, void* hip_stream) {
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   {
     int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-      c->ncu = n;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      c->dev = dev;
+      if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+        c->ncu = n;
+    }
     clear_stale_error();
+  }
+  if (c->dev >= 0 && c->dev < kMaxDevices) {
+    // device address of this device's static workspace (once per device)
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[c->dev]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        fprintf(stderr, "df_create: hipGetSymbolAddress(scratch): %s\n", hipGetErrorString(e));
+        delete c;
+        return DF_EHIP;
+      }
+      g_scratch_ptr[c->dev] = ptr;
+    }
   }
   hipError_t e = hipMalloc(&c->status, 256);
   if (e != hipSuccess) {
@@ -666,6 +695,32 @@ int df_build_jk(df_ctx* c, const double* B, int layout, int64_t naux, int64_t na
   mark(c, 1 + DF_STAGE_BOUND);
   if (c->ev_used < c->ev_cap) ++c->ev_used;
   return DF_OK;
+}
+
+int df_build_jk_noalloc(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao,
+                        const int32_t* b_exp, const double* C, int64_t nocc, double occ,
+                        const double* D, double* J, double* K, double* energies,
+                        double* err_bound) {
+  clear_stale_error();
+  int rc = check_shape(c, layout, naux, nao, nocc);
+  if (rc) return rc;
+  void* ptr = nullptr;
+  if (c->dev >= 0 && c->dev < kMaxDevices) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ptr = g_scratch_ptr[c->dev];
+  }
+  if (!ptr) return fail(c, DF_EHIP, "no static workspace on the context's device");
+  const size_t need = make_plan(c, naux, nao, nocc).total;
+  if (need > kStaticWsBytes)
+    return fail(c, DF_EWORKSPACE, "shape needs more than the 64 MiB static workspace");
+  char* const saved_ws = c->ws;
+  const size_t saved_bytes = c->ws_bytes;
+  c->ws = reinterpret_cast<char*>(ptr);
+  c->ws_bytes = kStaticWsBytes;
+  rc = df_build_jk(c, B, layout, naux, nao, b_exp, C, nocc, occ, D, J, K, energies, err_bound);
+  c->ws = saved_ws;
+  c->ws_bytes = saved_bytes;
+  return rc;
 }
 
 int df_prepare_b_size(int64_t naux, int64_t nao, int planes, size_t* bytes) {
