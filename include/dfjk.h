@@ -66,10 +66,10 @@ enum df_status {
  *             rows: element (mu, nu), mu >= nu, at mu (mu + 1) / 2 + nu (the
  *             stored form of Sec. 3.3; half the bytes).  nao <= 16383.  Taken
  *             by df_b_exponents, df_build_x, df_build_jk, df_build_jk_noalloc,
- *             df_prepare_b and df_debug_build_i32; results are bit-identical to
- *             the same build on the dense tensor, except rho (and so J and E_J),
- *             which may differ in FP64 rounding order.  Screening, the
- *             autotuner, the batched build and df_spot_check take DF_DENSE. */
+ *             df_prepare_b, df_spot_check and df_debug_build_i32; results are
+ *             bit-identical to the same build on the dense tensor, except rho
+ *             (and so J and E_J), which may differ in FP64 rounding order.
+ *             Screening, the autotuner and the batched build take DF_DENSE. */
 enum df_layout {
   DF_DENSE = 0,
   DF_PACKED = 1
@@ -373,21 +373,24 @@ int df_rule_slices(int level, int fp64_below_level);
  *   partials of the last df_build_jk with block precision set (kref as written
  *   by df_block_partials, e.g. of an all-FP64 build).
  * df_spot_check: the FP64 check of sampled blocks: for each host_blocks[i],
- *   recomputes K_b in native FP64 from B and C and writes
+ *   recomputes K_b in native FP64 from B (DF_DENSE or DF_PACKED) and C and writes
  *   err[i] = |occ| max |K_b - K_b(FP64)| / kfro for the partials of the last
  *   df_build_jk with block precision set.  Needs the build's workspace. */
 /* df_controller_allocate (host only, no GPU work): per-block slice counts at
  * the accuracy of one reference count.  pred [nblocks][8] (host) holds the
  * predicted log10 errors of every block for s = 1..8 (taken non-increasing in
  * s); the error budget is slack * sum_b 10^pred[b][s_ref-1], the predicted
- * error of all blocks at s_ref.  Starting from s = 1 everywhere, the block
+ * error of all blocks at s_ref.  cost [8] (host, may be NULL) is the cost of
+ * one block at s = 1..8 (NULL: s(s+1)/2, the digit products; a caller may
+ * pass measured build times).  Starting from s = 1 everywhere, the block
  * whose move to its next count with a strictly smaller predicted error
- * removes the most error per added digit product (s -> s' adds
- * s'(s'+1)/2 - s(s+1)/2 products) is moved, until the predicted total meets
- * the budget (or no block can improve).  s_ref == 0 gives 0 (native FP64)
- * for all. */
+ * removes the most error per added cost is moved, until the predicted total
+ * meets the budget (or no block can improve); a move that adds no cost beats
+ * every other (the largest error drop first among them).  Then every block
+ * takes the largest count that costs no more than its own.  s_ref == 0 gives
+ * 0 (native FP64) for all.  DF_EINVAL for a non-finite cost. */
 int df_controller_allocate(const float* pred, int64_t nblocks, int s_ref, double slack,
-                           int32_t* s_out);
+                           const double* cost, int32_t* s_out);
 int df_block_stats(df_ctx* ctx, const double* A, const double* A2, int64_t n, int64_t seglen,
                    double* out);
 int df_x_block_stats(df_ctx* ctx, int64_t naux, int64_t nao, int64_t nocc, double* out);
@@ -403,9 +406,9 @@ int df_choose_slices(df_ctx* ctx, const float* pred, int64_t n, double target, i
 int df_block_partials(df_ctx* ctx, int64_t naux, int64_t nao, int64_t nocc, double* out);
 int df_block_errors(df_ctx* ctx, int64_t naux, int64_t nao, int64_t nocc, double occ,
                     const double* kref, double kfro, double* err);
-int df_spot_check(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* C,
-                  int64_t nocc, double occ, double kfro, const int32_t* host_blocks, int nsample,
-                  double* err);
+int df_spot_check(df_ctx* ctx, const double* B, int layout, int64_t naux, int64_t nao,
+                  const double* C, int64_t nocc, double occ, double kfro,
+                  const int32_t* host_blocks, int nsample, double* err);
 
 /* Device status word (0, DF_ENONFINITE or DF_ENOTSPD) accumulated since the last call;
  * synchronises the context stream and clears the word. */

@@ -162,21 +162,26 @@ def block_errors(B, C, occ=2.0, pblk=64, slices=range(1, 9)):
     return out
 
 
-def allocate(pred, s_ref, slack=1.0):
+def allocate(pred, s_ref, slack=1.0, cost=None):
     """Per-block slice counts meeting the predicted error of a uniform s_ref.
 
     pred [nb][8]: predicted log10 errors per block for s = 1..8, taken
     non-increasing in s (running minimum).  Budget = slack * sum_b err_b(s_ref).
-    Greedy: from s = 1 everywhere, repeatedly move the block with the largest
-    predicted error drop per added digit product (s -> s' costs
-    s'(s'+1)/2 - s(s+1)/2 products) to s', the next count with a strictly
-    smaller predicted error, until the predicted total meets the budget.
+    cost [8]: the cost of one block at s = 1..8 (default s(s+1)/2, the digit
+    products; e.g. measured build times).  Greedy: from s = 1 everywhere,
+    repeatedly move the block with the largest predicted error drop per added
+    cost to s', the next count with a strictly smaller predicted error, until
+    the predicted total meets the budget; a move that adds no cost counts as
+    better than any that does (the larger error drop first among them).  Then
+    every block takes the largest count that costs no more than its own.
     s_ref = 0 -> all 0.
     """
     pred = np.asarray(pred, dtype=np.float32).astype(np.float64)
     nb = pred.shape[0]
     if s_ref == 0:
         return np.zeros(nb, dtype=np.int64)
+    c = (np.array([k * (k + 1) // 2 for k in range(1, N_OUT + 1)], dtype=np.float64)
+         if cost is None else np.asarray(cost, dtype=np.float64))
     err = np.minimum.accumulate(10.0 ** pred, axis=1)
     budget = 0.0
     for b in range(nb):                 # sums in block order, like the library
@@ -189,17 +194,25 @@ def allocate(pred, s_ref, slack=1.0):
             total += err[b, s[b] - 1]
         if not total > budget:
             break
-        best, gain, best_to = -1, 0.0, 0
+        best, best_free, gain, best_to = -1, False, 0.0, 0
         for b in range(nb):
             to = s[b] + 1
             while to <= N_OUT and not err[b, to - 1] < err[b, s[b] - 1]:
                 to += 1
             if to > N_OUT:
                 continue
-            g = (err[b, s[b] - 1] - err[b, to - 1]) / (to * (to + 1) // 2 - s[b] * (s[b] + 1) // 2)
-            if best < 0 or g > gain:
-                best, gain, best_to = b, g, to
+            drop = err[b, s[b] - 1] - err[b, to - 1]
+            dc = c[to - 1] - c[s[b] - 1]
+            free = not dc > 0.0
+            g = drop if free else drop / dc
+            if best < 0 or (free and not best_free) or (free == best_free and g > gain):
+                best, best_free, gain, best_to = b, free, g, to
         if best < 0:
             break
         s[best] = best_to
+    for b in range(nb):                 # counts that cost nothing more
+        for to in range(N_OUT, s[b], -1):
+            if not c[to - 1] > c[s[b] - 1]:
+                s[b] = to
+                break
     return s

@@ -70,9 +70,11 @@ SIGNATURES = {
     "df_block_partials": (_int, [_c_void_p, _i64, _i64, _i64, _c_void_p]),
     "df_block_errors": (_int, [_c_void_p, _i64, _i64, _i64, ctypes.c_double, _c_void_p,
                                ctypes.c_double, _c_void_p]),
-    "df_spot_check": (_int, [_c_void_p, _c_void_p, _i64, _i64, _c_void_p, _i64, ctypes.c_double,
-                             ctypes.c_double, ctypes.POINTER(ctypes.c_int32), _int, _c_void_p]),
+    "df_spot_check": (_int, [_c_void_p, _c_void_p, _int, _i64, _i64, _c_void_p, _i64,
+                             ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                             _int, _c_void_p]),
     "df_controller_allocate": (_int, [ctypes.POINTER(ctypes.c_float), _i64, _int, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int32)]),
     "df_screen": (_int, [_c_void_p, _c_void_p, _i64, _i64, _int, ctypes.c_double, _c_void_p,
                          _c_void_p, _c_void_p]),
@@ -321,11 +323,12 @@ class Context:
         self._check(self.lib.df_block_errors(self.h, naux, nao, nocc, float(occ), _ptr(kref),
                                              float(kfro), _ptr(err)), "df_block_errors")
 
-    def df_spot_check(self, B, C, occ, kfro, blocks, err):
-        naux, nao = B.shape[0], B.shape[1]
+    def df_spot_check(self, B, C, occ, kfro, blocks, err, layout=DF_DENSE, naux=None, nao=None):
+        naux, nao = _shape(B, layout, naux, nao)
         arr = (ctypes.c_int32 * len(blocks))(*[int(b) for b in blocks])
-        self._check(self.lib.df_spot_check(self.h, _ptr(B), naux, nao, _ptr(C), C.shape[1],
-                                           float(occ), float(kfro), arr, len(blocks), _ptr(err)),
+        self._check(self.lib.df_spot_check(self.h, _ptr(B), layout, naux, nao, _ptr(C),
+                                           C.shape[1], float(occ), float(kfro), arr, len(blocks),
+                                           _ptr(err)),
                     "df_spot_check")
 
     def df_screen(self, B, blk, tau, mask, chunks, norms=None):
@@ -434,14 +437,16 @@ def df_mlp_nparams():
     return load().df_mlp_nparams()
 
 
-def df_controller_allocate(pred, s_ref, slack=1.0):
-    """pred: host float array [nblocks][8] of predicted log10 errors; returns a list of s."""
+def df_controller_allocate(pred, s_ref, slack=1.0, cost=None):
+    """pred: host float array [nblocks][8] of predicted log10 errors; cost: None
+    or 8 per-block costs of s = 1..8; returns a list of s."""
     import numpy as np
     p = np.ascontiguousarray(pred, dtype=np.float32)
     nb = p.shape[0]
     out = (ctypes.c_int32 * nb)()
+    c = None if cost is None else (ctypes.c_double * 8)(*[float(v) for v in cost])
     rc = load().df_controller_allocate(p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), nb,
-                                       int(s_ref), float(slack), out)
+                                       int(s_ref), float(slack), c, out)
     if rc != DF_OK:
         raise DFError(rc, "df_controller_allocate: bad arguments")
     return list(out)

@@ -21,14 +21,16 @@ build overshoots its predicted error; when that estimate exceeds `margin`
 times the error budget (the predicted error of s_ref everywhere), the
 iteration is rebuilt by the plain rule (uniform s_ref).  The checks also
 feed back: a per-s correction (the largest log10 ratio of measured to
-predicted error seen at that s, decaying by `decay` per iteration) is added
-to the predictions before the next allocation.
+predicted error seen at that s, decaying by `decay` per iteration, never
+below a floor such as the network's own under-estimate quantile on its
+training samples) is added to the predictions before the next allocation.
 """
 import math
 
 import numpy as np
 
 from . import binding
+from .binding import DF_DENSE, DF_PACKED
 
 ACCURACY = {4: 2.0 ** -23, 3: 2.0 ** -31, 2: 2.0 ** -39, 1: 2.0 ** -47, 0: 2.0 ** -52}
 
@@ -59,13 +61,16 @@ class _Buffers:
 
 class BlockFeatures:
     """Per-run feature state: B's block statistics (once), X and D of the
-    previous iteration, K of the previous iteration."""
+    previous iteration, K of the previous iteration.  With packed B the
+    statistics of a block are those of its stored elements (the lower
+    triangles)."""
 
-    def __init__(self, ctx, B, naux, nao, nocc, pblk=64):
+    def __init__(self, ctx, B, naux, nao, nocc, pblk=64, layout=DF_DENSE):
         self.ctx, self.B = ctx, B
         self.naux, self.nao, self.nocc, self.pblk = naux, nao, nocc, pblk
         self.buf = _Buffers(B, naux, nao, nocc, pblk)
-        ctx.df_block_stats(B, self.buf.bstats, pblk * nao * nao)
+        per_aux = nao * (nao + 1) // 2 if layout == DF_PACKED else nao * nao
+        ctx.df_block_stats(B, self.buf.bstats, pblk * per_aux)
         self.have_prev = False
 
     def features(self, C, D, k, n_iter, de_rel, target, plain_s):
@@ -87,6 +92,25 @@ class BlockFeatures:
         self.have_prev = True
 
 
+def order_aux_blocks(ctx, B, pblk=64, layout=DF_DENSE, naux=None, nao=None):
+    """B with its aux blocks ordered by decreasing max |B_b| (one device copy),
+    and the order.  Blocks that the controller gives equal counts then sit
+    together, so the per-block build runs few, long launches; J, K and the
+    energies do not depend on the order of the aux index.  naux must be a
+    multiple of pblk."""
+    import torch
+    naux, nao = binding._shape(B, layout, naux, nao)
+    if naux % pblk:
+        raise ValueError("order_aux_blocks: naux must be a multiple of pblk")
+    per_aux = nao * (nao + 1) // 2 if layout == DF_PACKED else nao * nao
+    nb = naux // pblk
+    st = torch.empty((nb, 2), dtype=torch.float64, device=B.device)
+    ctx.df_block_stats(B, st, pblk * per_aux)
+    order = torch.argsort(st[:, 0], descending=True, stable=True)
+    out = B.reshape(nb, pblk * per_aux).index_select(0, order).reshape(B.shape)
+    return out, order
+
+
 def _energy(en):
     e = en.cpu().numpy()
     return float(e[0] + e[1])
@@ -99,16 +123,18 @@ def _rel_change(e_prev, e_now):
     return abs(d) if e_now == 0 else abs(d / e_now)
 
 
-def collect_samples(ctx, B, b_exp, orbitals, occ=2.0, pblk=64, slices=range(1, 9)):
+def collect_samples(ctx, B, b_exp, orbitals, occ=2.0, pblk=64, slices=range(1, 9),
+                    layout=DF_DENSE):
     """Training samples of one sequence of orbitals: for every iteration and
     block, the 16 features and the measured log10 block errors at each s in
     `slices` (mask 1 where measured and non-zero).  Returns float32 arrays
     x [n][16], t [n][8], m [n][8]."""
     import torch
-    naux, nao = B.shape[0], B.shape[1]
+    naux, nao = binding._shape(B, layout)
+    kw = dict(layout=layout, naux=naux, nao=nao)
     nocc = orbitals[0].shape[1]
     ctx.df_set_pblk(pblk)
-    fs = BlockFeatures(ctx, B, naux, nao, nocc, pblk)
+    fs = BlockFeatures(ctx, B, naux, nao, nocc, pblk, layout)
     b = fs.buf
     nb = b.nb
     kref = torch.empty((nb, nao, nao), dtype=torch.float64, device=B.device)
@@ -123,7 +149,7 @@ def collect_samples(ctx, B, b_exp, orbitals, occ=2.0, pblk=64, slices=range(1, 9
         # FP64 reference partials
         ctx.df_set_block_precision([0] * nb)
         ctx.ensure_workspace(naux, nao, nocc)
-        ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb)
+        ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb, **kw)
         ctx.df_block_partials(naux, nao, nocc, kref)
         ctx.df_block_stats(b.K, b.kfro, b.K.numel())
         e64 = _energy(b.en)
@@ -132,11 +158,14 @@ def collect_samples(ctx, B, b_exp, orbitals, occ=2.0, pblk=64, slices=range(1, 9
         fs.after_build(b.D, K64)
         t = np.zeros((nb, 8), dtype=np.float32)
         m = np.zeros((nb, 8), dtype=np.float32)
+        errs = torch.zeros((8, nb), dtype=torch.float64, device=B.device)
         for s in slices:
             ctx.df_set_block_precision([s] * nb)
-            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb)
-            ctx.df_block_errors(naux, nao, nocc, occ, kref, kfro, b.err)
-            err = b.err.cpu().numpy()
+            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb, **kw)
+            ctx.df_block_errors(naux, nao, nocc, occ, kref, kfro, errs[s - 1])
+        errs = errs.cpu().numpy()
+        for s in slices:
+            err = errs[s - 1]
             ok = err > 0
             t[ok, s - 1] = np.log10(err[ok])
             m[ok, s - 1] = 1.0
@@ -171,6 +200,24 @@ def train(ctx, x, t, m, steps=2000, batch=1024, lr=1e-3, seed=0, log_every=0):
     return params, losses
 
 
+def residual_floor(ctx, params, x, t, m, q=0.9):
+    """Per-s safety margin (decades, >= 0): the q-quantile over the training
+    samples of measured minus predicted log10 error at each s.  Added to the
+    predictions, it makes the allocation as cautious as the network's own
+    under-estimates on its training set."""
+    import torch
+    dx = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    y = torch.empty((x.shape[0], 8), dtype=torch.float32, device="cuda")
+    ctx.df_mlp_forward(params, dx, y)
+    r = t.astype(np.float64) - y.cpu().numpy().astype(np.float64)
+    out = np.zeros(8)
+    for s in range(8):
+        sel = m[:, s] > 0
+        if sel.any():
+            out[s] = max(0.0, float(np.quantile(r[sel, s], q)))
+    return out
+
+
 def evaluate(ctx, params, x, t, m):
     """Masked RMS error (in decades) of the predictions on (x, t, m)."""
     import torch
@@ -182,8 +229,24 @@ def evaluate(ctx, params, x, t, m):
     return float(np.sqrt((r * r).sum() / max(m.sum(), 1.0)))
 
 
+def build_costs(ctx, B, b_exp, C, occ, D, J, K, energies, err_bound, reps=3, layout=DF_DENSE):
+    """Measured time (ms) of the uniform build at s = 1..8 on this problem:
+    the cost table of the allocation (an X pass bound by reading B costs the
+    same at s = 1, 2 and 3, which digit products do not show)."""
+    from . import adaptive
+    naux, nao = binding._shape(B, layout)
+    args = (B, b_exp, C, occ, D, J, K, energies, err_bound)
+    ctx.df_set_block_precision(None)
+    out = []
+    for s in range(1, 9):
+        ctx.df_set_precision(s)
+        out.append(adaptive._timed_build(ctx, args, reps, layout=layout, naux=naux, nao=nao))
+    return out
+
+
 def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below_level=0,
-                   spot=2, margin=1.0, decay=0.9, fp64_check=False, seed=0, s_refs=None):
+                   spot=2, margin=1.0, decay=0.9, fp64_check=False, seed=0, s_refs=None,
+                   layout=DF_DENSE, floor=None, slack=1.0, cost=None, min_gain=0.0):
     """The controlled sequence.  Per iteration: plain-rule reference count,
     features, prediction, per-block allocation, build, FP64 spot check (and
     fallback to the uniform reference count).  Returns per-iteration records
@@ -191,13 +254,22 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
 
     s_refs: the reference counts to use instead of running the rule on this
     sequence's own energies (e.g. those of a plain run, to compare the two at
-    the same reference accuracy in every iteration)."""
+    the same reference accuracy in every iteration).  floor: per-s margins
+    (decades) below which the correction never decays (e.g. residual_floor).
+    slack: the allocation's budget as a multiple of the predicted error of the
+    reference count.  cost: the allocation's per-s cost table (e.g.
+    build_costs; None: digit products).  The controller leaves to the plain
+    rule (one uniform build at s_ref, no spot check) the first iteration,
+    which has no previous X and K for its features, and every iteration whose
+    allocation the cost table prices less than `min_gain` times the reference
+    count's cost below it (the controller's own work would eat the saving)."""
     import torch
     import dfinputs
-    naux, nao = B.shape[0], B.shape[1]
+    naux, nao = binding._shape(B, layout)
+    kw = dict(layout=layout, naux=naux, nao=nao)
     nocc = orbitals[0].shape[1]
     ctx.df_set_pblk(pblk)
-    fs = BlockFeatures(ctx, B, naux, nao, nocc, pblk)
+    fs = BlockFeatures(ctx, B, naux, nao, nocc, pblk, layout)
     b = fs.buf
     nb = b.nb
     spot_err = torch.empty(max(spot, 1), dtype=torch.float64, device=B.device)
@@ -206,38 +278,49 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
     K64 = torch.empty_like(b.K) if fp64_check else None
     en64 = torch.empty_like(b.en) if fp64_check else None
     level, e_prev, e_prev2 = 4, None, None
-    corr = np.zeros(8)  # per-s correction of the predictions (decades, >= 0)
+    floor = np.zeros(8) if floor is None else np.asarray(floor, dtype=np.float64)
+    corr = floor.copy()  # per-s correction of the predictions (decades, >= floor)
     recs = []
     for k, C in enumerate(orbitals):
-        corr *= decay
+        corr = np.maximum(corr * decay, floor)
         s_ref = binding.df_rule_slices(level, fp64_below_level) if s_refs is None else s_refs[k]
         ctx.df_density(C, occ, b.D)
+        # timed: everything the controller adds (features, prediction, the
+        # allocation's host round trip, spot check, fallback, and the block
+        # statistics of this iteration that the next one's features read)
         ev0.record()
+        plain = s_ref == 0 or k == 0
         fallback = False
-        if s_ref == 0:
-            sb = [0] * nb
-            ctx.df_set_block_precision(sb)
-            ctx.ensure_workspace(naux, nao, nocc)
-            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb)
-            pred_h = None
-        else:
+        pred_h = None
+        if not plain:
             de = _rel_change(e_prev2, e_prev)
             feat = fs.features(C, b.D, k, len(orbitals), de, ACCURACY[level], s_ref)
             ctx.df_mlp_forward(params, feat, b.pred)
             pred_h = b.pred.cpu().numpy() + corr[None, :].astype(np.float32)
-            sb = binding.df_controller_allocate(pred_h, s_ref)
+            sb = binding.df_controller_allocate(pred_h, s_ref, slack, cost)
+            if cost is not None:
+                # the saving the cost table promises for this allocation
+                saved = cost[s_ref - 1] - sum(cost[v - 1] for v in sb) / nb
+                plain = saved < min_gain * cost[s_ref - 1]
+        if plain:
+            sb = [s_ref] * nb
+            ctx.df_set_block_precision(None)
+            ctx.df_set_precision(s_ref)
+            ctx.ensure_workspace(naux, nao, nocc)
+            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb, **kw)
+        else:
             ctx.df_set_block_precision(sb)
             ctx.ensure_workspace(naux, nao, nocc)
-            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb)
+            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb, **kw)
             if spot > 0:
                 ctx.df_block_stats(b.K, b.kfro, b.K.numel())
                 kfro = math.sqrt(float(b.kfro.cpu()[0, 1]))
                 blocks = dfinputs.spot_blocks(nb, spot, k, seed)
                 if kfro > 0:
-                    ctx.df_spot_check(B, C, occ, kfro, blocks, spot_err[:len(blocks)])
+                    ctx.df_spot_check(B, C, occ, kfro, blocks, spot_err[:len(blocks)], **kw)
                     se = spot_err[:len(blocks)].cpu().numpy()
                     err_pred = np.minimum.accumulate(10.0 ** pred_h.astype(np.float64), axis=1)
-                    budget = float(err_pred[:, s_ref - 1].sum())
+                    budget = slack * float(err_pred[:, s_ref - 1].sum())
                     excess = sum(max(0.0, float(se[i]) - float(err_pred[blk, sb[blk] - 1]))
                                  for i, blk in enumerate(blocks))
                     if nb / len(blocks) * excess > margin * budget:
@@ -249,19 +332,21 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
             if fallback:
                 sb = [s_ref] * nb
                 ctx.df_set_block_precision(sb)
-                ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb)
+                ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb, **kw)
+        fs.after_build(b.D, b.K)
         ev1.record()
         e_now = _energy(b.en)
         ms = ev0.elapsed_time(ev1)
-        fs.after_build(b.D, b.K)
         rec = dict(iteration=k, level=level, s_ref=s_ref, slices=list(sb), fallback=fallback,
+                   mode="plain" if plain else "controller",
                    correction=[round(float(v), 3) for v in corr],
                    work=int(sum(s * (s + 1) // 2 for s in sb)),
                    work_ref=int(nb * s_ref * (s_ref + 1) // 2), energy=e_now, ms=ms,
                    err_bound=float(b.eb.cpu()[0]))
         if fp64_check:
             ctx.df_set_block_precision([0] * nb)
-            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, K64, en64, b.eb)
+            ctx.ensure_workspace(naux, nao, nocc)
+            ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, K64, en64, b.eb, **kw)
             nrm = float(torch.linalg.norm(K64))
             rec["k_maxabs_rel_fro"] = float((b.K - K64).abs().max()) / nrm if nrm else 0.0
             rec["energy_fp64"] = _energy(en64)

@@ -20,6 +20,12 @@ struct df_ctx {
   int pblk = 64;
   int k_groups_req = 0;
   int k_groups_used = 0;
+  // per-block statistics of X recorded by the last build's slicing of X
+  // (valid for that shape and workspace only)
+  bool xst_ok = false;
+  int64_t xst_naux = 0, xst_nao = 0, xst_nocc = 0;
+  int xst_pblk = 0;
+  const char* xst_ws = nullptr;
   int x_ksub_req = 0;  // X chunk depth asked for (0 = autotuned or default)
   int extra = 0;       // anti-diagonals of digit pairs kept beyond a + b = s + 1
   int ncu = 256;  // compute units of the context's device
@@ -97,7 +103,7 @@ struct Plan {
   int packed;  // B stored as DF_PACKED (set by common_checks)
   size_t off_bexp, off_fcol, off_dC, off_X, off_xmax, off_F, off_Xd, off_rho, off_rowdot,
       off_Jp, off_Kp, off_bsc, off_esc, off_dD, off_gexp, off_h, off_wd, off_Sj, off_drho,
-      off_Xs, off_Ks, off_xsmax, total;
+      off_Xs, off_Ks, off_xsmax, off_xss, total;
 };
 
 size_t carve(size_t& cur, size_t bytes) {
@@ -159,6 +165,7 @@ Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
   p.off_dC = carve(cur, (size_t)kMaxSlices * p.ncp * p.kp);
   p.off_X = carve(cur, (size_t)p.nb * p.pblk * nao * nocc * 8);  // blocked layout
   p.off_xmax = carve(cur, (size_t)p.nb * nao * 8);
+  p.off_xss = carve(cur, (size_t)p.nb * (p.kbp / 64) * (p.nao_pad / 16) * 8);
   p.off_F = carve(cur, (size_t)p.nb * p.nao_pad * 4);
   p.off_Xd = carve(cur, (size_t)kMaxSlices * p.nb * p.nao_pad * p.kbp);
   p.off_rho = carve(cur, (size_t)naux * 8);
@@ -248,11 +255,24 @@ void mark(df_ctx* c, int idx) {
     if (e_ != hipSuccess) return hip_fail(c, e_, where); \
   } while (0)
 
+// squared-sum slots of X per aux block written by the slicing of X
+int64_t xss_slots(const Plan& p) { return (int64_t)(p.kbp / 64) * (p.nao_pad / 16); }
+
+void set_xstats(df_ctx* c, const Plan& p, bool ok) {
+  c->xst_ok = ok;
+  c->xst_naux = p.naux;
+  c->xst_nao = p.nao;
+  c->xst_nocc = p.nocc;
+  c->xst_pblk = p.pblk;
+  c->xst_ws = c->ws;
+}
+
 // X (and the per-(block, mu) max of |X|) at the context precision.
 int run_x(df_ctx* c, const Plan& p, const double* B, const int32_t* b_exp, const double* C,
           double* X) {
   const int s = c->slices;
   unsigned long long* xmax = at<unsigned long long>(c, p.off_xmax);
+  set_xstats(c, p, false);  // the workspace maxima now belong to the caller's X
   DF_HIP(launch_fill_u64(c->stream, xmax, (int64_t)p.nb * p.nao, 0ull), "fill xmax");
   if (s == 0) {
     DF_HIP(launch_x_fp64(c->stream, B, p.naux, (int)p.nao, C, (int)p.nocc, X, 0, xmax, p.pblk,
@@ -285,10 +305,13 @@ int k_stages(df_ctx* c, const Plan& p, const double* X, double occ, double* K, i
     DF_HIP(launch_xmax_to_exp(st, xmax, (int64_t)p.nb * nao, F), "xmax_to_exp");
     *fstride = (int)nao;
   } else {
-    DF_HIP(launch_slice_x(st, s, X, naux, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp, xmax, F, Xd),
+    DF_HIP(launch_slice_x(st, s, X, naux, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp, xmax, F, Xd,
+                          at<double>(c, p.off_xss)),
            "slice_x");
     *fstride = p.nao_pad;
   }
+  // the per-block statistics of X come with the slicing (no FP64 path)
+  set_xstats(c, p, s != 0);
   mark(c, 1 + DF_STAGE_SLICE_X);
   if (s == 0) {
     DF_HIP(launch_k_fp64(st, X, naux, (int)nao, (int)nocc, p.pblk, p.nb, p.groups, Kp), "k_fp64");
@@ -397,7 +420,8 @@ int xk_stages_blocks(df_ctx* c, const Plan& p, const double* B, const int32_t* b
              "k_fp64");
     } else {
       DF_HIP(launch_slice_x(st, r.s, Xr, P1 - P0, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp,
-                            xmax + (int64_t)r.b0 * nao, F + (int64_t)r.b0 * p.nao_pad, Xd),
+                            xmax + (int64_t)r.b0 * nao, F + (int64_t)r.b0 * p.nao_pad, Xd,
+                            at<double>(c, p.off_xss) + (int64_t)r.b0 * xss_slots(p)),
              "slice_x");
       DF_HIP(launch_k_int8(st, r.s, Xd, F + (int64_t)r.b0 * p.nao_pad, nbr, (int)nao, p.nao_pad,
                            p.kbp, nbr, Kp + (int64_t)r.b0 * nn, nullptr, c->extra),
@@ -405,6 +429,9 @@ int xk_stages_blocks(df_ctx* c, const Plan& p, const double* B, const int32_t* b
     }
   }
   mark(c, 1 + DF_STAGE_K);
+  bool all_int8 = true;
+  for (const Run& r : runs) all_int8 = all_int8 && r.s != 0;
+  set_xstats(c, p, all_int8);
   c->k_groups_used = p.nb;
   DF_HIP(launch_k_reduce(st, Kp, p.nb, (int)nao, occ, K), "k_reduce");
   mark(c, 1 + DF_STAGE_K_REDUCE);
@@ -841,6 +868,14 @@ int df_x_block_stats(df_ctx* c, int64_t naux, int64_t nao, int64_t nocc, double*
   if (!out) return fail(c, DF_EINVAL, "null out");
   const Plan p = make_plan(c, naux, nao, nocc);
   if (!c->ws || c->ws_bytes < p.total) return fail(c, DF_EWORKSPACE, "workspace too small");
+  if (c->xst_ok && c->xst_ws == c->ws && c->xst_naux == naux && c->xst_nao == nao &&
+      c->xst_nocc == nocc && c->xst_pblk == p.pblk) {
+    // recorded by the build: the maxima of its X pass, the squares summed by its slicing
+    DF_HIP(launch_xstats_from(c->stream, at<unsigned long long>(c, p.off_xmax),
+                              at<double>(c, p.off_xss), p.nb, (int)nao, xss_slots(p), out),
+           "xstats_from");
+    return DF_OK;
+  }
   // blocked X: block b holds rows mu of pblk * nocc entries; the last block
   // uses only its first (naux - (nb - 1) pblk) * nocc entries of each row
   const int64_t rowlen = (int64_t)p.pblk * nocc;
@@ -940,11 +975,11 @@ int df_block_errors(df_ctx* c, int64_t naux, int64_t nao, int64_t nocc, double o
   return DF_OK;
 }
 
-int df_spot_check(df_ctx* c, const double* B, int64_t naux, int64_t nao, const double* C,
-                  int64_t nocc, double occ, double kfro, const int32_t* host_blocks, int nsample,
-                  double* err) {
+int df_spot_check(df_ctx* c, const double* B, int layout, int64_t naux, int64_t nao,
+                  const double* C, int64_t nocc, double occ, double kfro,
+                  const int32_t* host_blocks, int nsample, double* err) {
   clear_stale_error();
-  const int rc = check_shape(c, DF_DENSE, naux, nao, nocc);
+  const int rc = check_shape(c, layout, naux, nao, nocc);
   if (rc) return rc;
   if (!B || !C || !host_blocks || !err || nsample < 1) return fail(c, DF_EINVAL, "bad arguments");
   if (!(kfro > 0.0) || isinf(kfro)) return fail(c, DF_EINVAL, "kfro must be positive and finite");
@@ -955,6 +990,7 @@ int df_spot_check(df_ctx* c, const double* B, int64_t naux, int64_t nao, const d
     if (host_blocks[i] < 0 || host_blocks[i] >= p.nb) return fail(c, DF_EINVAL, "block index out of range");
   hipStream_t st = c->stream;
   const int64_t nn = nao * nao;
+  const int64_t bstride = layout == DF_PACKED ? nao * (nao + 1) / 2 : nn;  // per aux index
   double* Xs = at<double>(c, p.off_Xs);
   double* Ks = at<double>(c, p.off_Ks);
   unsigned long long* xm = at<unsigned long long>(c, p.off_xsmax);
@@ -963,8 +999,8 @@ int df_spot_check(df_ctx* c, const double* B, int64_t naux, int64_t nao, const d
     const int64_t P0 = (int64_t)b * p.pblk;
     const int64_t P1 = std::min<int64_t>(P0 + p.pblk, naux);
     DF_HIP(launch_fill_u64(st, xm, nao, 0ull), "fill");
-    DF_HIP(launch_x_fp64(st, B + P0 * nn, P1 - P0, (int)nao, C, (int)nocc, Xs, 1, xm, p.pblk,
-                         nullptr, nullptr),
+    DF_HIP(launch_x_fp64(st, B + P0 * bstride, P1 - P0, (int)nao, C, (int)nocc, Xs, 1, xm,
+                         p.pblk, nullptr, nullptr, nullptr, layout == DF_PACKED),
            "x_fp64");
     DF_HIP(launch_k_fp64(st, Xs, P1 - P0, (int)nao, (int)nocc, p.pblk, 1, 1, Ks), "k_fp64");
     DF_HIP(launch_block_err(st, at<double>(c, p.off_Kp) + b * nn, Ks, (int)nao, fabs(occ) / kfro,
@@ -1369,9 +1405,14 @@ int df_rule_slices(int level, int fp64_below_level) {
 }
 
 int df_controller_allocate(const float* pred, int64_t nblocks, int s_ref, double slack,
-                           int32_t* s_out) {
+                           const double* cost, int32_t* s_out) {
   if (!pred || !s_out || nblocks < 1 || s_ref < 0 || s_ref > kMaxSlices || !(slack > 0.0))
     return DF_EINVAL;
+  double cs[kMaxSlices];
+  for (int k = 0; k < kMaxSlices; ++k) {
+    cs[k] = cost ? cost[k] : (double)((k + 1) * (k + 2) / 2);
+    if (!std::isfinite(cs[k])) return DF_EINVAL;
+  }
   if (s_ref == 0) {
     for (int64_t b = 0; b < nblocks; ++b) s_out[b] = 0;
     return DF_OK;
@@ -1396,17 +1437,24 @@ int df_controller_allocate(const float* pred, int64_t nblocks, int s_ref, double
     double total = 0.0;  // the predicted total, in block order
     for (int64_t b = 0; b < nblocks; ++b) total += E(b, s_out[b]);
     if (!(total > budget)) break;
+    // the move with the largest error drop per added cost; a move that adds
+    // no cost beats every other (the largest drop first among them)
     int64_t best = -1;
     int best_to = 0;
+    bool best_free = false;
     double gain = 0.0;
     for (int64_t b = 0; b < nblocks; ++b) {
       const int sb = s_out[b];
       int to = sb + 1;
       while (to <= kMaxSlices && !(E(b, to) < E(b, sb))) ++to;
       if (to > kMaxSlices) continue;
-      const double g = (E(b, sb) - E(b, to)) / (double)(to * (to + 1) / 2 - sb * (sb + 1) / 2);
-      if (best < 0 || g > gain) {
+      const double drop = E(b, sb) - E(b, to);
+      const double dc = cs[to - 1] - cs[sb - 1];
+      const bool free = !(dc > 0.0);
+      const double g = free ? drop : drop / dc;
+      if (best < 0 || (free && !best_free) || (free == best_free && g > gain)) {
         best = b;
+        best_free = free;
         gain = g;
         best_to = to;
       }
@@ -1414,6 +1462,13 @@ int df_controller_allocate(const float* pred, int64_t nblocks, int s_ref, double
     if (best < 0) break;
     s_out[best] = best_to;
   }
+  // then every block takes the largest count that costs no more than its own
+  for (int64_t b = 0; b < nblocks; ++b)
+    for (int to = kMaxSlices; to > s_out[b]; --to)
+      if (!(cs[to - 1] > cs[s_out[b] - 1])) {
+        s_out[b] = to;
+        break;
+      }
   return DF_OK;
 }
 
@@ -1465,6 +1520,7 @@ int df_debug_build_i32(df_ctx* c, const double* B, int layout, int64_t naux, int
   int8_t* Xd = at<int8_t>(c, p.off_Xd);
   DF_HIP(launch_slice_x(st, s, X, naux, (int)nao, (int)nocc, p.pblk, p.nao_pad, p.kbp, xmax, F, Xd),
          "slice_x");
+  set_xstats(c, p, false);
   DF_HIP(launch_k_int8(st, s, Xd, F, p.nb, (int)nao, p.nao_pad, p.kbp, p.groups,
                        at<double>(c, p.off_Kp), k_sums, c->extra),
          "k_int8");

@@ -14,6 +14,33 @@ constexpr int OW1 = 0, OB1 = OW1 + NI * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH,
 constexpr int MT = 32;  // samples per workgroup
 
 // ---------------------------------------------------------------- statistics
+// Block statistics of X recorded by the build itself: out[b] = (max over mu of
+// xmax[b][mu] (bit patterns of non-negative doubles), the sum of the block's
+// nslot squared-sum slots, lane-strided then a fixed shuffle tree).  One wave
+// per block.
+__global__ __launch_bounds__(64) void k_xstats_from(const unsigned long long* __restrict__ xmax,
+                                                    const double* __restrict__ xss, int nao,
+                                                    int64_t nslot, double* __restrict__ out) {
+  const int b = blockIdx.x, l = threadIdx.x;
+  unsigned long long m = 0;
+  for (int mu = l; mu < nao; mu += 64) {
+    const unsigned long long v = xmax[(int64_t)b * nao + mu];
+    m = v > m ? v : m;
+  }
+  double sq = 0.0;
+  for (int64_t i = l; i < nslot; i += 64) sq += xss[b * nslot + i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(m, off);
+    m = o > m ? o : m;
+    sq += __shfl_xor(sq, off);
+  }
+  if (l == 0) {
+    out[2 * b] = abs_max_bits_to_double(m);
+    out[2 * b + 1] = sq;
+  }
+}
+
 // partial[seg][split] = (max |a - a2|, sum (a - a2)^2) over the split's slice of
 // segment seg (segments of seglen elements, the last one ragged).  In the last
 // segment only the first last_valid elements of every run of rowlen count
@@ -329,6 +356,14 @@ inline unsigned gcap(int64_t n, int64_t c = 4096) {
 }  // namespace
 
 int mlp_nparam() { return NPARAM; }
+
+hipError_t launch_xstats_from(hipStream_t st, const unsigned long long* xmax, const double* xss,
+                              int nb, int nao, int64_t nslot, double* out) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xstats_from, dim3((unsigned)nb), dim3(64), 0, st, xmax, xss, nao, nslot,
+                     out);
+  return hipGetLastError();
+}
 
 hipError_t launch_seg_stats(hipStream_t st, const double* A, const double* A2, int64_t n,
                             int64_t seglen, int64_t rowlen, int64_t last_valid, double* partial,

@@ -172,10 +172,17 @@ hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, i
 // anti-diagonal sums g = 2..s+1 of the tiles.  packed: B as [naux][nao(nao+1)/2],
 // the lower triangle of each B_P by rows (no screening masks; 64-wide chunks).
 // extra: anti-diagonals kept beyond a + b = s + 1 (0 or 1; 64-wide chunks).)
-// X in the blocked layout.
+// X in the blocked layout.  xss (optional): the sums of squares of X in
+// slots of 16 rows x 64 values, [nb][kbp / 64][nao_pad / 16] (slot order of
+// the block's X digits: step, then rows).
 hipError_t launch_slice_x(hipStream_t st, int s, const double* Xb, int64_t naux, int nao,
                           int nocc, int pblk, int nao_pad, int kbp,
-                          const unsigned long long* xmax, int32_t* F, int8_t* Xd);
+                          const unsigned long long* xmax, int32_t* F, int8_t* Xd,
+                          double* xss = nullptr);
+// out[b] = (max over mu of the |X| maxima xmax[b][mu], the sum of block b's
+// nslot slots of xss in a fixed order) for b < nb.
+hipError_t launch_xstats_from(hipStream_t st, const unsigned long long* xmax, const double* xss,
+                              int nb, int nao, int64_t nslot, double* out);
 // Workgroups of the INT8 K kernel for s slices that one CU holds at once.
 int k_int8_resident(int s);
 // dbg (test export, may be null): [s][nb][nao][nao] int32 anti-diagonal sums

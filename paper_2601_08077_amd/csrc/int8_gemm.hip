@@ -550,13 +550,21 @@ __global__ __launch_bounds__(256) void k_slice_x(const double* __restrict__ Xb, 
                                                  int nao_pad, int kbp,
                                                  const unsigned long long* __restrict__ xmax,
                                                  int32_t* __restrict__ F,
-                                                 int8_t* __restrict__ Xd) {
+                                                 int8_t* __restrict__ Xd,
+                                                 double* __restrict__ xss) {
   const int nks = kbp >> 6;
   const int64_t total = (int64_t)nb * nks * nao_pad * 4;
   const int64_t plane = (int64_t)nb * nao_pad * kbp;
   const int64_t kfull = (int64_t)pblk * nocc;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  // every thread runs the same number of rounds; with xss given, each wave
+  // also sums the squares of its 16 rows x 64 values of X (one aux block, one
+  // 64-wide k step: the 64 consecutive idx of a wave) into its own slot
+  // xss[idx / 64] (no atomics; total is a multiple of 64)
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < total;
+       i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx = i0 + threadIdx.x;
+    double sq = 0.0;
+    if (idx < total) {
     const int part = (int)(idx & 3);
     const int64_t rest = idx >> 2;
     const int mu = (int)(rest % nao_pad);
@@ -595,6 +603,17 @@ __global__ __launch_bounds__(256) void k_slice_x(const double* __restrict__ Xb, 
 #pragma unroll
     for (int a = 0; a < S; ++a)
       *reinterpret_cast<uint4*>(dst + (int64_t)a * plane) = make_uint4(r0[a].x, r0[a].y, r1[a].x, r1[a].y);
+    if (xss) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) sq = fma(v[j], v[j], sq);
+    }
+    }
+    if (xss) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off);
+      const int64_t w0 = i0 + (threadIdx.x & ~63);
+      if ((threadIdx.x & 63) == 0 && w0 < total) xss[w0 >> 6] = sq;
+    }
   }
 }
 
@@ -903,7 +922,7 @@ hipError_t launch_x_int8(hipStream_t st, int s, const double* B, int64_t naux, i
 
 hipError_t launch_slice_x(hipStream_t st, int s, const double* X, int64_t naux, int nao,
                           int nocc, int pblk, int nao_pad, int kbp,
-                          const unsigned long long* xmax, int32_t* F, int8_t* Xd) {
+                          const unsigned long long* xmax, int32_t* F, int8_t* Xd, double* xss) {
   const int nb = (int)((naux + pblk - 1) / pblk);
   const int64_t total = (int64_t)nb * nao_pad * (kbp / 16);  // threads (16 k each)
   if (total <= 0) return hipSuccess;
@@ -911,7 +930,7 @@ hipError_t launch_slice_x(hipStream_t st, int s, const double* X, int64_t naux, 
   if (g > 65536) g = 65536;
 #define DFJK_SLICE_X(SS)                                                                      \
   hipLaunchKernelGGL((k_slice_x<SS>), dim3((unsigned)g), dim3(256), 0, st, X, naux, nao, nocc, \
-                     pblk, nb, nao_pad, kbp, xmax, F, Xd)
+                     pblk, nb, nao_pad, kbp, xmax, F, Xd, xss)
   switch (s) {
     case 1: DFJK_SLICE_X(1); break;
     case 2: DFJK_SLICE_X(2); break;

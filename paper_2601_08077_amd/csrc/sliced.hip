@@ -73,13 +73,34 @@ __global__ __launch_bounds__(256) void k_slice_planes(const double* __restrict__
   }
 }
 
-// X = B C from the B digit planes.  Tile: 64 rows x 16 NF columns; wave w owns
-// rows 16 (w & 3) .. +15 and column fragments [NFW (w >> 2), +NFW) (NH column
-// halves, NF = NH NFW).  Lane (q, r) holds the 16 bytes k0 + 16 q .. +15 of its
-// row in every plane (the same k order as the C digits in LDS, natural k), so
-// the MFMA sums over the 64 k of a chunk.  With D digits given, waves of half
-// 0 also accumulate the row dots of rho per anti-diagonal with v_dot4 on the
-// same fragments (exact int32), then recombine them in FP64.
+// 16 bytes per lane from a buffer resource (byte offset voff + soff) straight
+// into LDS: lane i of the wave writes bytes 16 i .. 16 i + 15 after the
+// wave-uniform LDS address lds_dst.  Completion is counted by vmcnt.
+__device__ __forceinline__ void copy16_lds(__amdgpu_buffer_rsrc_t r, void* lds_dst, int voff,
+                                           int soff) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds_dst, 16,
+                                           voff, soff, 0, 0);
+}
+
+// X = B C from the B digit planes, both operands copied from memory straight
+// into LDS (buffer loads to LDS: no per-value VALU work).  Tile: 64 rows x NT
+// columns (NT = 16 NFW NH); wave w owns rows 16 (w & 3) .. +15 and column
+// fragments [NFW (w >> 2), +NFW).  A stage holds, for one 64-wide k chunk, the
+// S planes of the tile's rows [64][64 B] and of its C columns [NT][64 B]; the
+// four 16-byte units of row (or column) r sit in the slots unit ^ ((r >> 1) & 3)
+// (the swizzle is made by choosing which unit each lane copies: one copy
+// instruction fills 16 rows, lane l row l >> 2, slot l & 3).  Two stages, each
+// its own __shared__ array (so that the compiler can tell the stage being
+// filled from the one being read): after the barrier of chunk c the copies of
+// chunk c + 1 are issued into the stage chunk c - 1 used, and land while chunk
+// c is multiplied; one barrier per chunk.  (Measured: a third stage, which
+// leaves one workgroup per CU where two stages leave two, was slower at s = 3
+// and no faster at s = 5.)  Lane (q, r) of an A fragment holds the 16 bytes
+// k0 + 16 q .. +15 of its row, natural k order (the C digits are in natural
+// order too).  With D digits given, waves of half 0 of the first column tile
+// also accumulate the row dots of rho per anti-diagonal with v_dot4 on their
+// A fragments and D fragments read from memory (exact int32), then recombine
+// them in FP64.
 template <int S, int NFW, int NH>
 __global__ __launch_bounds__(256 * NH) void k_x_dig(
     const int8_t* __restrict__ Bd, int64_t bplane, int64_t M, int ldk,
@@ -87,45 +108,77 @@ __global__ __launch_bounds__(256 * NH) void k_x_dig(
     const int32_t* __restrict__ f_col, int nocc, double* __restrict__ X,
     unsigned long long* __restrict__ xmax, int nao, int pblk,
     const int8_t* __restrict__ Dd, const int32_t* __restrict__ d_exp, double* __restrict__ rowdot) {
-  constexpr int NF = NFW * NH, NT = 16 * NF, ROW = 64, NTHR = 256 * NH;
-  constexpr int CUNITS = S * NT * 4;
-  constexpr int CPER = (CUNITS + NTHR - 1) / NTHR;
-  // C digits in two LDS stages (one barrier per chunk); the A and D fragments
-  // come straight from global memory, PF chunks ahead in registers
-  // (measured per s: the deeper pipeline pays for 4 <= s <= 7; at s = 3 the
-  // extra registers cost more occupancy than they hide, at s = 8 they spill)
-  constexpr int NBUF = (S >= 4 && S <= 7) ? 2 : 1;
-  constexpr int PF = S == 4 ? 2 : 1;
-  constexpr bool DPF = S >= 4 && S <= 6;  // D fragments prefetched too
-  __shared__ __attribute__((aligned(16))) int8_t Cs[NBUF][S][NT][ROW];
-  static_assert(sizeof(Cs) <= kLdsLimit, "C stages exceed LDS");
+  constexpr int NF = NFW * NH, NT = 16 * NF, NW = 4 * NH;
+  constexpr int ACOPY = 4 * S, CCOPY = NF * S;  // copies of a chunk (16 rows / columns each)
+  constexpr int PA = (ACOPY + NW - 1) / NW, PC = (CCOPY + NW - 1) / NW;
+  constexpr int ASZ = S * 64 * 64, CSZ = S * NT * 64;
+  __shared__ __attribute__((aligned(16))) int8_t As0[ASZ];
+  __shared__ __attribute__((aligned(16))) int8_t As1[ASZ];
+  __shared__ __attribute__((aligned(16))) int8_t Cs0[CSZ];
+  __shared__ __attribute__((aligned(16))) int8_t Cs1[CSZ];
+  static_assert(2 * (ASZ + CSZ) <= kLdsLimit, "X stages exceed LDS");
   const int t = threadIdx.x, w = t >> 6, l = t & 63, q = l >> 4, r16 = l & 15;
   const int wr = w & 3, half = w >> 2;
-  int64_t m0 = (int64_t)blockIdx.x * 64;
-  if (nao % 64 == 0) {  // workgroups running together share the rows of D
+  // tiles in the logical order (row tile, column tile), handed to the XCDs
+  // in contiguous ranges: the column tiles of one row tile share its B digits
+  // in one L2, and neighbouring row tiles (consecutive P at one mu tile when
+  // nao is a multiple of 64) share the rows of D
+  const int ncol = ncp / NT;
+  const int64_t lid = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t rt = lid / ncol;
+  const int ct = (int)(lid - rt * ncol);
+  int64_t m0 = rt * 64;
+  if (nao % 64 == 0) {
     const int64_t naux = M / nao;
-    const int64_t mt = blockIdx.x / naux, P = blockIdx.x - mt * naux;
+    const int64_t mt = rt / naux, P = rt - mt * naux;
     m0 = P * nao + mt * 64;
   }
-  const int n0 = blockIdx.y * NT;
+  const int n0 = ct * NT;
   const int64_t arow = m0 + wr * 16 + r16;
   const bool aok = arow < M;
-  const int8_t* asrc = Bd + (aok ? arow : 0) * (int64_t)ldk + q * 16;
-  const bool want_rd = Dd != nullptr && blockIdx.y == 0 && half == 0;
+  const bool want_rd = Dd != nullptr && ct == 0 && half == 0;
   const int mu_a = aok ? (int)(arow % nao) : 0;
   const int8_t* dsrc = (Dd ? Dd : Bd) + (int64_t)mu_a * ldk + q * 16;
   const int64_t dplane = (int64_t)nao * ldk;
   const int nch = ldk / 64;
 
-  const int8_t* csrc[CPER];
-  int cdst[CPER];
+  // this wave's copies: A copy j = w + NW i (plane j >> 2, rows 16 (j & 3)
+  // .. +15 of the tile), C copy j = w + NW i (plane j / NF, columns 16 (j % NF)
+  // .. +15); lane l copies row (column) l >> 2 of the group, global unit
+  // (l & 3) ^ ((l >> 3) & 3), into slot l & 3
+  const int cvoff = (l >> 2) * ldk + (((l & 3) ^ ((l >> 3) & 3)) << 4);
+  __amdgpu_buffer_rsrc_t crA[PA], crC[PC];
+  int cdA[PA], cdC[PC];
 #pragma unroll
-  for (int i = 0; i < CPER; ++i) {
-    const int u = t + NTHR * i;
-    const int uu = u < CUNITS ? u : 0;
-    const int a = uu / (NT * 4), rem = uu - a * (NT * 4), col = rem >> 2, part = rem & 3;
-    csrc[i] = dC + ((int64_t)a * ncp + n0 + col) * ldk + part * 16;
-    cdst[i] = (a * NT + col) * ROW + swz(col, part);
+  for (int i = 0; i < PA; ++i) {
+    const int j = w + NW * i;
+    const int jj = j < ACOPY ? j : 0;
+    const int a = jj >> 2, grp = jj & 3;
+    const int64_t r0 = m0 + 16 * grp;
+    const int64_t nrow = M - r0 < 0 ? 0 : (M - r0 > 16 ? 16 : M - r0);
+    crA[i] = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int8_t*>(Bd + a * bplane + (nrow ? r0 : 0) * (int64_t)ldk), (short)0,
+        (int)(nrow * ldk), 0x00020000);
+    cdA[i] = (a * 64 + 16 * grp) * 64;
+  }
+#pragma unroll
+  for (int i = 0; i < PC; ++i) {
+    const int j = w + NW * i;
+    const int jj = j < CCOPY ? j : 0;
+    const int a = jj / NF, grp = jj - a * NF;
+    crC[i] = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int8_t*>(dC + ((int64_t)a * ncp + n0 + 16 * grp) * ldk), (short)0, 16 * ldk,
+        0x00020000);
+    cdC[i] = (a * NT + 16 * grp) * 64;
+  }
+#define DFJK_XD_COPY(AS, CS, CC)                                                            \
+  {                                                                                         \
+    _Pragma("unroll") for (int i = 0; i < PA; ++i) {                                        \
+      if (w + NW * i < ACOPY) copy16_lds(crA[i], (AS) + cdA[i], cvoff, (CC) * 64);          \
+    }                                                                                       \
+    _Pragma("unroll") for (int i = 0; i < PC; ++i) {                                        \
+      if (w + NW * i < CCOPY) copy16_lds(crC[i], (CS) + cdC[i], cvoff, (CC) * 64);          \
+    }                                                                                       \
   }
 
   i32x4 acc[S][NFW];
@@ -136,140 +189,61 @@ __global__ __launch_bounds__(256 * NH) void k_x_dig(
   int rdi[S];
 #pragma unroll
   for (int g = 0; g < S; ++g) rdi[g] = 0;
+  i32x4 dcur[S];
+#pragma unroll
+  for (int b = 0; b < S; ++b) dcur[b] = i32x4{0, 0, 0, 0};
+#define DFJK_XD_LOADD(DST, CC)                                                              \
+  {                                                                                         \
+    if (want_rd) {                                                                          \
+      _Pragma("unroll") for (int b = 0; b < S; ++b) DST[b] =                                \
+          *reinterpret_cast<const i32x4*>(dsrc + b * dplane + (CC) * 64);                   \
+    }                                                                                       \
+  }
+  // chunk CC (stage AS, CS): wait for its copies, meet at the barrier, load
+  // chunk CC's D rows (used after the MFMAs), start the copies of chunk CC + 1
+  // into the stage chunk CC - 1 used (ASN, CSN), then multiply
+#define DFJK_XD_STEP(AS, CS, ASN, CSN, CC)                                                  \
+  {                                                                                         \
+    const int cc = (CC);                                                                    \
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");             \
+    DFJK_XD_LOADD(dcur, cc)                                                                 \
+    if (cc + 1 < nch) DFJK_XD_COPY(ASN, CSN, cc + 1)                                        \
+    const int8_t* As = (AS);                                                                \
+    const int8_t* Cs = (CS);                                                                \
+    const int arw = wr * 16 + r16;                                                          \
+    i32x4 acur[S];                                                                          \
+    _Pragma("unroll") for (int a = 0; a < S; ++a) acur[a] =                                 \
+        *reinterpret_cast<const i32x4*>(As + (a * 64 + arw) * 64 + swz(arw, q));            \
+    _Pragma("unroll") for (int f = 0; f < NFW; ++f) {                                       \
+      const int col = (half * NFW + f) * 16 + r16;                                          \
+      _Pragma("unroll") for (int b = 0; b < S; ++b) {                                       \
+        const i32x4 bf =                                                                    \
+            *reinterpret_cast<const i32x4*>(Cs + (b * NT + col) * 64 + swz(col, q));        \
+        _Pragma("unroll") for (int a = 0; a < S - b; ++a) acc[a + b][f] =                   \
+            __builtin_amdgcn_mfma_i32_16x16x64_i8(acur[a], bf, acc[a + b][f], 0, 0, 0);     \
+      }                                                                                     \
+    }                                                                                       \
+    if (want_rd) {                                                                          \
+      _Pragma("unroll") for (int a = 0; a < S; ++a)                                         \
+      _Pragma("unroll") for (int b = 0; b < S - a; ++b) {                                   \
+        int v = rdi[a + b];                                                                 \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j) v =                                   \
+            __builtin_amdgcn_sdot4(acur[a][j], dcur[b][j], v, false);                       \
+        rdi[a + b] = v;                                                                     \
+      }                                                                                     \
+    }                                                                                       \
+  }
 
-  i32x4 af[PF][S], dp[PF][S], cpre[CPER];
-#define DFJK_XD_LOADA(SLOT, CC)                                                            \
-  {                                                                                        \
-    const int kb = (CC) * 64;                                                              \
-    _Pragma("unroll") for (int a = 0; a < S; ++a) af[SLOT][a] =                            \
-        *reinterpret_cast<const i32x4*>(asrc + a * bplane + kb);                           \
-    if (DPF && want_rd) {                                                                  \
-      _Pragma("unroll") for (int b = 0; b < S; ++b) dp[SLOT][b] =                          \
-          *reinterpret_cast<const i32x4*>(dsrc + b * dplane + kb);                         \
-    }                                                                                      \
+  // prologue: the copies of chunk 0; a step's copies go into the stage the
+  // previous step read
+  DFJK_XD_COPY(As0, Cs0, 0)
+  for (int c = 0; c < nch; c += 2) {
+    DFJK_XD_STEP(As0, Cs0, As1, Cs1, c)
+    if (c + 1 < nch) DFJK_XD_STEP(As1, Cs1, As0, Cs0, c + 1)
   }
-#define DFJK_XD_LOADC(CC)                                                                  \
-  {                                                                                        \
-    const int kb = (CC) * 64;                                                              \
-    _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                     \
-      if (t + NTHR * i < CUNITS) cpre[i] = *reinterpret_cast<const i32x4*>(csrc[i] + kb);  \
-    }                                                                                      \
-  }
-#define DFJK_XD_STOREC(BUF)                                                                \
-  {                                                                                        \
-    _Pragma("unroll") for (int i = 0; i < CPER; ++i) {                                     \
-      if (t + NTHR * i < CUNITS)                                                           \
-        *reinterpret_cast<i32x4*>(&Cs[BUF][0][0][0] + cdst[i]) = cpre[i];                  \
-    }                                                                                      \
-  }
-  if constexpr (NBUF == 2) {
-  DFJK_XD_LOADA(0, 0)
-  DFJK_XD_LOADC(0)
-  DFJK_XD_STOREC(0)
-  if (PF == 2 && nch > 1) DFJK_XD_LOADA(PF - 1, 1)
-  if (nch > 1) DFJK_XD_LOADC(1)
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nch) DFJK_XD_STOREC(buf ^ 1)  // stage buf ^ 1 was last read before the barrier
-    i32x4 acur[S], dcur[S];
-#pragma unroll
-    for (int a = 0; a < S; ++a) {
-      acur[a] = af[0][a];
-      if (DPF) dcur[a] = dp[0][a];
-    }
-    if (!DPF && want_rd) {
-#pragma unroll
-      for (int b = 0; b < S; ++b)
-        dcur[b] = *reinterpret_cast<const i32x4*>(dsrc + b * dplane + c * 64);
-    }
-    if (PF == 2) {
-#pragma unroll
-      for (int a = 0; a < S; ++a) {
-        af[0][a] = af[PF - 1][a];
-        if (DPF) dp[0][a] = dp[PF - 1][a];
-      }
-      if (c + 2 < nch) DFJK_XD_LOADA(PF - 1, c + 2)
-    } else if (c + 1 < nch) {
-      DFJK_XD_LOADA(0, c + 1)
-    }
-    if (c + 2 < nch) DFJK_XD_LOADC(c + 2)
-    if (want_rd) {
-#pragma unroll
-      for (int a = 0; a < S; ++a)
-#pragma unroll
-        for (int b = 0; b < S - a; ++b) {
-          int v = rdi[a + b];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) v = __builtin_amdgcn_sdot4(acur[a][j], dcur[b][j], v, false);
-          rdi[a + b] = v;
-        }
-    }
-#pragma unroll
-    for (int f = 0; f < NFW; ++f) {
-      const int col = (half * NFW + f) * 16 + r16;
-      i32x4 bf[S];
-#pragma unroll
-      for (int b = 0; b < S; ++b)
-        bf[b] = *reinterpret_cast<const i32x4*>(&Cs[buf][b][col][swz(col, q)]);
-#pragma unroll
-      for (int a = 0; a < S; ++a)
-#pragma unroll
-        for (int b = 0; b < S - a; ++b)
-          acc[a + b][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(acur[a], bf[b], acc[a + b][f], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  } else {
-    // one LDS stage: store, barrier, multiply, barrier
-    DFJK_XD_LOADA(0, 0)
-    DFJK_XD_LOADC(0)
-    for (int c = 0; c < nch; ++c) {
-      const int buf = 0;
-      __syncthreads();
-      DFJK_XD_STOREC(0)
-      __syncthreads();
-      i32x4 acur[S], dcur[S];
-#pragma unroll
-      for (int a = 0; a < S; ++a) acur[a] = af[0][a];
-      if (c + 1 < nch) {
-        DFJK_XD_LOADA(0, c + 1)
-        DFJK_XD_LOADC(c + 1)
-      }
-      if (want_rd) {
-#pragma unroll
-        for (int b = 0; b < S; ++b)
-          dcur[b] = *reinterpret_cast<const i32x4*>(dsrc + b * dplane + c * 64);
-      }
-    if (want_rd) {
-#pragma unroll
-      for (int a = 0; a < S; ++a)
-#pragma unroll
-        for (int b = 0; b < S - a; ++b) {
-          int v = rdi[a + b];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) v = __builtin_amdgcn_sdot4(acur[a][j], dcur[b][j], v, false);
-          rdi[a + b] = v;
-        }
-    }
-#pragma unroll
-    for (int f = 0; f < NFW; ++f) {
-      const int col = (half * NFW + f) * 16 + r16;
-      i32x4 bf[S];
-#pragma unroll
-      for (int b = 0; b < S; ++b)
-        bf[b] = *reinterpret_cast<const i32x4*>(&Cs[buf][b][col][swz(col, q)]);
-#pragma unroll
-      for (int a = 0; a < S; ++a)
-#pragma unroll
-        for (int b = 0; b < S - a; ++b)
-          acc[a + b][f] = __builtin_amdgcn_mfma_i32_16x16x64_i8(acur[a], bf[b], acc[a + b][f], 0, 0, 0);
-    }
-    }
-  }
-#undef DFJK_XD_STOREC
-#undef DFJK_XD_LOADC
-#undef DFJK_XD_LOADA
+#undef DFJK_XD_STEP
+#undef DFJK_XD_LOADD
+#undef DFJK_XD_COPY
 
   if (want_rd) {
     // exact sums over the four lane groups of the row, then its recombination
@@ -523,15 +497,18 @@ hipError_t x_dig_s(hipStream_t st, const int8_t* Bd, int64_t bplane, int64_t M, 
                    int nocc, double* X, unsigned long long* xmax, int nao, int pblk,
                    const int8_t* Dd, const int32_t* d_exp, double* rowdot) {
   const unsigned gx = (unsigned)((M + 63) / 64);
-#define DFJK_XD(NFW, NH)                                                                      \
-  hipLaunchKernelGGL((k_x_dig<S, NFW, NH>), dim3(gx, ncp / (16 * NFW * NH)), dim3(256 * NH), 0, \
-                     st, Bd, bplane, M, ldk, b_exp, dC, ncp, f_col, nocc, X, xmax, nao, pblk, Dd, \
-                     d_exp, rowdot)
+#define DFJK_XD(NFW, NH)                                                                        \
+  do {                                                                                          \
+    constexpr int NT_ = 16 * (NFW) * (NH);                                                      \
+    hipLaunchKernelGGL((k_x_dig<S, NFW, NH>), dim3(gx * (unsigned)(ncp / NT_)),                 \
+                       dim3(256 * (NH)), 0, st, Bd, bplane, M, ldk, b_exp, dC, ncp, f_col, nocc, \
+                       X, xmax, nao, pblk, Dd, d_exp, rowdot);                                  \
+  } while (0)
   if (ncp % 96 == 0) {
-    if (S <= 2) DFJK_XD(6, 1);
+    if constexpr (S <= 2) DFJK_XD(6, 1);
     else DFJK_XD(3, 2);
   } else if (ncp % 64 == 0) {
-    if (S <= 3) DFJK_XD(4, 1);
+    if constexpr (S <= 3) DFJK_XD(4, 1);
     else DFJK_XD(2, 2);
   } else {
     DFJK_XD(1, 2);

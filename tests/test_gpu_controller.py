@@ -231,6 +231,7 @@ def test_block_errors_and_spot_check(torch_dev, ctx):
     en = torch.empty(2, dtype=torch.float64, device="cuda")
     eb = torch.empty(1, dtype=torch.float64, device="cuda")
     kref = torch.empty((nb, nao, nao), dtype=torch.float64, device="cuda")
+    Bp = _dev(torch, dfinputs.pack_lower(p["B"]))
     try:
         ctx.df_set_block_precision([0] * nb)
         ctx.ensure_workspace(naux, nao, nocc)
@@ -249,6 +250,10 @@ def test_block_errors_and_spot_check(torch_dev, ctx):
             ctx.df_spot_check(B, C, 2.0, kfro, [6, 0, 3], spot)
             torch.cuda.synchronize()
             e = err.cpu().numpy()
+            assert np.array_equal(spot.cpu().numpy(), e[[6, 0, 3]])
+            # packed B: the same FP64 products in the same order
+            from paper_2601_08077_amd import DF_PACKED
+            ctx.df_spot_check(Bp, C, 2.0, kfro, [6, 0, 3], spot, layout=DF_PACKED)
             assert np.array_equal(spot.cpu().numpy(), e[[6, 0, 3]])
             ref = 10.0 ** oracle_err[:, s - 1]
             # the FP64 references (GPU MFMA vs NumPy) differ by FP64 rounding

@@ -72,3 +72,4 @@ def test_trained_controller_beats_plain_rule(torch_dev):
     assert w_ctl < 0.9 * w_plain
     assert abs(ctl[-1]["energy_err"]) <= 4.0 * abs(plain[-1]["energy_err"]) + 1e-12
     ctx.close()
+

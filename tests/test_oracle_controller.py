@@ -189,6 +189,46 @@ def test_allocate_non_monotone_predictions_use_running_minimum():
     assert list(s) == [6, 6, 6]
 
 
+def test_allocate_with_digit_product_costs_is_the_default():
+    pred = _slopes(30, 4)
+    costs = [k * (k + 1) // 2 for k in range(1, 9)]
+    for s_ref in (2, 4, 7):
+        assert list(ctl.allocate(pred, s_ref, cost=costs)) == list(ctl.allocate(pred, s_ref))
+
+
+def test_allocate_with_constant_cost_takes_the_most_accurate_count():
+    # every count costs the same: nothing is gained by dropping precision
+    pred = _slopes(12, 5)
+    assert list(ctl.allocate(pred, 3, cost=[1.0] * 8)) == [8] * 12
+
+
+def test_allocate_with_flat_low_costs_never_goes_below_the_flat_range():
+    """Build time that does not fall below s = 3 (an X pass bound by reading B):
+    counts 1 and 2 cost what 3 costs, so no block is left below 3, the budget
+    is still met, and the cost is no more than the reference's."""
+    pred = _slopes(40, 6)
+    err = 10.0 ** pred
+    cost = [5.0, 5.0, 5.0, 6.5, 8.0, 9.6, 11.3, 13.0]
+    for s_ref in (3, 4, 6):
+        s = ctl.allocate(pred, s_ref, cost=cost)
+        assert s.min() >= 3
+        assert err[np.arange(40), s - 1].sum() <= err[:, s_ref - 1].sum() * (1 + 1e-12)
+        assert sum(cost[v - 1] for v in s) <= 40 * cost[s_ref - 1] + 1e-9
+    # at s_ref = 3 that is the reference everywhere
+    assert list(ctl.allocate(pred, 3, cost=cost)) == [3] * 40
+
+
+def test_allocate_cost_pass_by_hand():
+    """Two blocks, costs 1, 1, 2, 4, ...: block 0 (large errors) must move up,
+    block 1 (tiny errors) stays low but takes the free count 2."""
+    pred = np.array([[-1, -3, -5, -7, -9, -11, -13, -15],
+                     [-20, -22, -24, -26, -28, -30, -32, -34]], dtype=np.float64)
+    cost = [1.0, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0]
+    s = ctl.allocate(pred, 3, cost=cost)
+    # budget 1e-5 + 1e-24; block 0 needs 3 (1e-5), block 1 is free at 2
+    assert list(s) == [3, 2]
+
+
 def test_library_allocate_matches_oracle():
     from paper_2601_08077_amd.binding import df_controller_allocate
     rng = np.random.default_rng(9)
@@ -199,3 +239,7 @@ def test_library_allocate_matches_oracle():
             for slack in (1.0, 2.0):
                 got = df_controller_allocate(pred, s_ref, slack)
                 assert got == list(ctl.allocate(pred, s_ref, slack))
+            cost = np.sort(rng.uniform(1.0, 10.0, 8))
+            cost[:3] = cost[2]                        # a flat low range
+            got = df_controller_allocate(pred, s_ref, 1.0, cost)
+            assert got == list(ctl.allocate(pred, s_ref, 1.0, cost))
