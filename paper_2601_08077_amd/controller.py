@@ -344,7 +344,9 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
                    work_ref=int(nb * s_ref * (s_ref + 1) // 2), energy=e_now, ms=ms,
                    err_bound=float(b.eb.cpu()[0]))
         if fp64_check:
-            ctx.df_set_block_precision([0] * nb)
+            # the same FP64 reference as the plain sequence's check (uniform s = 0)
+            ctx.df_set_block_precision(None)
+            ctx.df_set_precision(0)
             ctx.ensure_workspace(naux, nao, nocc)
             ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, K64, en64, b.eb, **kw)
             nrm = float(torch.linalg.norm(K64))

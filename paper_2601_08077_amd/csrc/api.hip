@@ -141,7 +141,8 @@ Plan make_plan(const df_ctx* c, int64_t naux, int64_t nao, int64_t nocc) {
   p.nb = (int)((naux + p.pblk - 1) / p.pblk);
   p.nao_pad = (int)round_up(nao, 64);
   p.kbp = (int)round_up((int64_t)p.pblk * nocc, 64);
-  p.ncp = nocc <= 32 ? 32 : (nocc <= 64 ? 64 : (int)round_up(nocc, 96));
+  p.ncp = nocc <= 32 ? 32 : nocc <= 64 ? 64 : nocc <= 96 ? 96 : nocc <= 128 ? 128
+                                                               : (int)round_up(nocc, 96);
   p.kp = (int)round_up(nao, 64);
   const int nt = p.nao_pad / 64;
   const int tiles = nt * (nt + 1) / 2;

@@ -110,7 +110,7 @@ __device__ __forceinline__ void digit_rows8(const double* v, int e, uint2* out) 
 // a few spilled words), which measured faster than 150 VGPRs at one.
 template <int S, int NF, bool FULLK, int KSUB, bool PK, int E>
 __global__ __launch_bounds__(512)
-__attribute__((amdgpu_waves_per_eu((PK && S <= 3 && KSUB == 1) ? 4 : 1))) void k_x_int8(
+__attribute__((amdgpu_waves_per_eu((PK && S <= 3 && KSUB == 1 && NF <= 6) ? 4 : 1))) void k_x_int8(
     const double* __restrict__ B, int64_t M, int K, const int32_t* __restrict__ b_exp,
     const int8_t* __restrict__ dC, int ncp, int kp, const int32_t* __restrict__ f_col, int nocc,
     double* __restrict__ X, int xlayout, unsigned long long* __restrict__ xmax, int nao, int pblk,
@@ -142,21 +142,34 @@ __attribute__((amdgpu_waves_per_eu((PK && S <= 3 && KSUB == 1) ? 4 : 1))) void k
   const int lrow = 8 * w + (l >> 3), lm = l & 7;  // loader: tile row, lane within row
   // Workgroups that run together share the basis-row tile mu0..mu0+63 (and so
   // the same rows of D, which stay in L2) and differ in the aux index P.
-  int64_t m0 = (int64_t)blockIdx.x * 64;
+  // With several column tiles (gridDim.y) the tiles are numbered (row tile,
+  // column tile) and handed to the XCDs in contiguous ranges, so that the
+  // column tiles of one row tile read its B rows from one L2.
+  const int ncol = gridDim.y;
+  int64_t rt = blockIdx.x;
+  int ct = 0;
+  if (ncol > 1) {
+    const int64_t lid = xcd_order(blockIdx.x + (int64_t)blockIdx.y * gridDim.x,
+                                  (int64_t)gridDim.x * ncol);
+    rt = lid / ncol;
+    ct = (int)(lid - rt * ncol);
+  } else if (PK) {
+    rt = xcd_order(blockIdx.x, gridDim.x);
+  }
+  int64_t m0 = rt * 64;
   int64_t ptile = 0;  // PK: the tile's aux index; mu0 its first row
   int mu0 = 0;
   if constexpr (PK) {
     const int nmt = (nao + 63) >> 6;
-    const int64_t lid = xcd_order(blockIdx.x, gridDim.x);
-    ptile = lid / nmt;
-    mu0 = (int)(lid - ptile * nmt) * 64;
+    ptile = rt / nmt;
+    mu0 = (int)(rt - ptile * nmt) * 64;
     m0 = ptile * nao + mu0;
   } else if (nao % 64 == 0) {
     const int64_t naux = M / nao;
-    const int64_t mt = blockIdx.x / naux, P = blockIdx.x - mt * naux;
+    const int64_t mt = rt / naux, P = rt - mt * naux;
     m0 = P * nao + mt * 64;
   }
-  const int n0 = blockIdx.y * NT;
+  const int n0 = ct * NT;
   // Rows past M (PK: past nao) read an in-bounds row; their digits and sums
   // are discarded.
   const int64_t arow = m0 + lrow;
@@ -498,7 +511,7 @@ __attribute__((amdgpu_waves_per_eu((PK && S <= 3 && KSUB == 1) ? 4 : 1))) void k
     rd += __shfl_xor(rd, 1);
     rd += __shfl_xor(rd, 2);
     rd += __shfl_xor(rd, 4);
-    if (lm == 0 && aok && blockIdx.y == 0) rowdot[arow] = rd;
+    if (lm == 0 && aok && ct == 0) rowdot[arow] = rd;
   }
 
   // Recombination, X store, and the per-(block, mu) running max of |X|.
@@ -849,19 +862,28 @@ hipError_t launch_x_sk(hipStream_t st, const double* B, int64_t M, int nao, cons
   // PK: one tile per (P, 64 rows of B_P); else 64 consecutive rows of the
   // stacked (P, mu) rows
   const unsigned gx = PK ? (unsigned)(M / nao * ((nao + 63) / 64)) : (unsigned)((M + 63) / 64);
-  if (ncp % 96 == 0) {
-    hipLaunchKernelGGL((k_x_int8<S, 6, FULLK, KSUB, PK, E>), dim3(gx, ncp / 96), dim3(512), 0, st, B,
-                       M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D,
-                       rowdot, cmask, dbg);
-  } else if (ncp % 64 == 0) {
-    hipLaunchKernelGGL((k_x_int8<S, 4, FULLK, KSUB, PK, E>), dim3(gx, ncp / 64), dim3(512), 0, st, B,
-                       M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D,
-                       rowdot, cmask, dbg);
-  } else {
-    hipLaunchKernelGGL((k_x_int8<S, 2, FULLK, KSUB, PK, E>), dim3(gx, ncp / 32), dim3(512), 0, st, B,
-                       M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, nao, pblk, D,
-                       rowdot, cmask, dbg);
+#define DFJK_XK(NF_)                                                                             \
+  hipLaunchKernelGGL((k_x_int8<S, NF_, FULLK, KSUB, PK, E>), dim3(gx, ncp / (16 * (NF_))),        \
+                     dim3(512), 0, st, B, M, nao, b_exp, dC, ncp, kp, f_col, nocc, X, xlayout, xmax, \
+                     nao, pblk, D, rowdot, cmask, dbg)
+  // one column tile over 128 or 192 columns where the stages fit in LDS (B is
+  // then read and sliced once), else tiles of 96, 64 or 32 columns
+  if constexpr (S <= 4 && KSUB == 1) {
+    if (ncp == 192) {
+      DFJK_XK(12);
+      return hipGetLastError();
+    }
   }
+  if constexpr (S + E <= 6 && KSUB == 1) {
+    if (ncp == 128) {
+      DFJK_XK(8);
+      return hipGetLastError();
+    }
+  }
+  if (ncp % 96 == 0) DFJK_XK(6);
+  else if (ncp % 64 == 0) DFJK_XK(4);
+  else DFJK_XK(2);
+#undef DFJK_XK
   return hipGetLastError();
 }
 

@@ -43,6 +43,7 @@ SHAPES = [  # nao, naux, nocc, pblk (ragged nao and naux, one and several row ti
     (128, 90, 20, 64),
     (130, 66, 33, 64),
     (200, 30, 100, 16),
+    (150, 24, 140, 64),              # 192 padded columns
 ]
 
 

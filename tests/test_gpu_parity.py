@@ -121,6 +121,8 @@ SHAPES = [
     (130, 65, 100, 64, True),
     (1, 1, 1, 64, False),
     (128, 70, 40, 64, True),         # nao a multiple of 64: the two-stage X path, two mu blocks
+    (128, 30, 120, 64, True),        # 128 padded columns: one 128-column tile (s <= 6) or two
+    (160, 20, 150, 16, True),        # 192 padded columns: one 192-column tile (s <= 4) or two
 ]
 
 
