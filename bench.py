@@ -225,7 +225,7 @@ def adaptive_workload(args):
            "final_energy_err": recs[-1]["energy_err"],
            "iterations": recs}
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def scf_workload(args):
@@ -290,7 +290,7 @@ def scf_workload(args):
            "levels_adaptive": [r["level"] for r in runs["adaptive"]],
            "iterations": runs}
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def _ctl_problem(ctx, nao, seed, L, pblk=64):
@@ -421,7 +421,7 @@ def controller_workload(args):
            "calibration_ms": {str(k): v for k, v in times.items()},
            "iterations_plain": plain, "iterations_controller": ctl}
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def batched_workload(args):
@@ -512,7 +512,7 @@ def batched_workload(args):
            "autotune_seconds": t_tune, "kept_block_fraction_mean": float(np.mean(kept)),
            "flops_alg_total": F}
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -527,6 +527,9 @@ def main():
     ap.add_argument("--no-sliced", action="store_true",
                     help="skip the sliced-mode levels (B as digit planes, digit rho and J)")
     ap.add_argument("--cpu-aux", type=int, default=64)
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the synthetic SCF, adaptive-sequence and batched workloads that "
+                         "the default run summarises after the headline")
     ap.add_argument("--workload", choices=("jk", "adaptive", "controller", "batched", "scf"),
                     default="jk",
                     help="jk: one J/K build per step (default); adaptive: the 20-iteration "
@@ -571,14 +574,11 @@ def main():
         del src, dst
         log("copy calibration: 1 GiB read + 1 GiB written")
 
-    if args.workload == "adaptive":
-        return adaptive_workload(args)
-    if args.workload == "controller":
-        return controller_workload(args)
-    if args.workload == "batched":
-        return batched_workload(args)
-    if args.workload == "scf":
-        return scf_workload(args)
+    workloads = {"adaptive": adaptive_workload, "controller": controller_workload,
+                 "batched": batched_workload, "scf": scf_workload}
+    if args.workload in workloads:
+        print(json.dumps(workloads[args.workload](args)), flush=True)
+        return
 
     from paper_2601_08077_amd import DF_DENSE, DF_PACKED
     cfg = dfinputs.CONFIG1
@@ -765,6 +765,20 @@ def main():
         log(f"cpu baseline: oracle on {args.cpu_aux} aux rows")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_aux, nao, nocc, cfg["L"])
     ctx.close()
+    if not args.no_workloads:
+        # the shorter workloads, summarised in the same record (each in its own
+        # context, after the benchmark tensor is freed)
+        del B, C, D, J, K, K64, J64, be, be_p, p
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["workloads"] = {}
+        for name in ("scf", "adaptive", "batched"):
+            log(f"workload {name}")
+            rec = workloads[name](args)
+            out["workloads"][name] = {k: v for k, v in rec.items() if k not in
+                                      ("iterations", "metric", "n_gpus", "higher_is_better",
+                                       "scaling", "vs_baseline", "data")}
+            torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

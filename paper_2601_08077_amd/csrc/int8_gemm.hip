@@ -110,7 +110,7 @@ __device__ __forceinline__ void digit_rows8(const double* v, int e, uint2* out) 
 // a few spilled words), which measured faster than 150 VGPRs at one.
 template <int S, int NF, bool FULLK, int KSUB, bool PK, int E>
 __global__ __launch_bounds__(512)
-__attribute__((amdgpu_waves_per_eu((PK && S <= 3 && KSUB == 1 && NF <= 6) ? 4 : 1))) void k_x_int8(
+__attribute__((amdgpu_waves_per_eu((PK && S <= 3 && KSUB == 1 && NF <= 8) ? 4 : 1))) void k_x_int8(
     const double* __restrict__ B, int64_t M, int K, const int32_t* __restrict__ b_exp,
     const int8_t* __restrict__ dC, int ncp, int kp, const int32_t* __restrict__ f_col, int nocc,
     double* __restrict__ X, int xlayout, unsigned long long* __restrict__ xmax, int nao, int pblk,
