@@ -165,7 +165,7 @@ def adaptive_workload(args):
     import numpy as np
     import torch
     import dfinputs
-    from paper_2601_08077_amd import Context, adaptive
+    from paper_2601_08077_amd import DF_PACKED, Context, adaptive
 
     cfg = dfinputs.CONFIG2
     nao, naux, nocc, n_iter = cfg["nao"], cfg["naux"], cfg["nocc"], cfg["n_iter"]
@@ -186,11 +186,19 @@ def adaptive_workload(args):
     chol_ms, whiten_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     log(f"metric Cholesky {chol_ms:.2f} ms, whitening {whiten_ms:.1f} ms")
     del T
+    # whitening acts on the aux index only, so every B_P stays symmetric: the
+    # sequence runs on its packed lower triangles
+    Bd = B
+    B = dfinputs.pack_lower(Bd)
+    del Bd
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    kw = dict(layout=DF_PACKED, naux=naux, nao=nao)
     ctx.df_set_workspace(None)
     ctx.df_set_pblk(64)
     ctx.ensure_workspace(naux, nao, nocc)
     be = torch.empty(naux * nao, dtype=torch.int32, device="cuda")
-    ctx.df_b_exponents(B, be)
+    ctx.df_b_exponents(B, be, **kw)
     rng = np.random.default_rng(0)
     C0, _ = dfinputs.make_orbitals(rng, nao, nocc)
     orbs_h = dfinputs.perturbed_orbitals(C0, n_iter, seed=0)
@@ -201,9 +209,10 @@ def adaptive_workload(args):
     en = torch.empty(2, dtype=torch.float64, device="cuda")
     eb = torch.empty(1, dtype=torch.float64, device="cuda")
     ctx.df_density(orbs[0], 2.0, D)
-    times, below = adaptive.calibrate(ctx, B, be, orbs[0], 2.0, D, J, K, en, eb)
+    times, below = adaptive.calibrate(ctx, B, be, orbs[0], 2.0, D, J, K, en, eb, layout=DF_PACKED)
     log(f"calibration ms {times}; FP64 from level {below} down")
-    recs = adaptive.run_sequence(ctx, B, be, orbs, fp64_below_level=below, fp64_check=True)
+    recs = adaptive.run_sequence(ctx, B, be, orbs, fp64_below_level=below, fp64_check=True,
+                                 layout=DF_PACKED)
     for r in recs:
         log(f"it {r['iteration']:2d} level {r['level']} s {r['slices']} {r['ms']:.2f} ms "
             f"E {r['energy']:.12f} dE(fp64) {r['energy_err']:.2e}")
@@ -216,7 +225,8 @@ def adaptive_workload(args):
            "dtype": "int8 x int8 -> int32, f64 recombination (adaptive), f64 fallback",
            "data": "synthetic",
            "config": {"workload": "adaptive-precision sequence, nao 1024 naux 4096 nocc 128, "
-                                  "20 iterations, eps 1e-2 -> 1e-8, metric W = A A^T / naux + I",
+                                  "20 iterations, eps 1e-2 -> 1e-8, metric W = A A^T / naux + I, "
+                                  "packed B",
                       "fp64_below_level": below},
            "metric_cholesky_ms": chol_ms, "whitening_ms": whiten_ms,
            "calibration_ms": {str(k): v for k, v in times.items()},

@@ -655,11 +655,13 @@ __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
                                                 int32_t* __restrict__ dbg) {
   constexpr int ROW = 64;             // 64 B rows, 16-byte units swizzled (swz)
   constexpr int NCP = 2 * S * 4;      // 1 KB copies per step (2 panels x S planes x 4)
-  constexpr int CPW = (NCP + 7) / 8;  // per wave; waves past the last copy fill spare rows
+  constexpr int CPW = NCP / 8;        // per wave: S, the same for every wave
+  static_assert(NCP % 8 == 0, "every wave issues the same number of copies");
   // stages as separate arrays (the compiler can tell the stage being copied
-  // into from the one being read); rows [panel][a][64], then 16 spare rows
-  __shared__ __attribute__((aligned(16))) int8_t L0[2 * S * 64 + 16][ROW];
-  __shared__ __attribute__((aligned(16))) int8_t L1[2 * S * 64 + 16][ROW];
+  // into from the one being read); rows [panel][a][64].  Two stages of 16 S KB:
+  // two workgroups per CU up to s = 5.
+  __shared__ __attribute__((aligned(16))) int8_t L0[2 * S * 64][ROW];
+  __shared__ __attribute__((aligned(16))) int8_t L1[2 * S * 64][ROW];
   static_assert(sizeof(L0) + sizeof(L1) <= kLdsLimit, "K stages exceed LDS");
   // group-major logical order, dealt to the XCDs in consecutive ranges: the
   // tiles of one group (which stream the same X_b panels) share an L2
@@ -681,13 +683,12 @@ __global__ __launch_bounds__(512) void k_k_int8(const int8_t* __restrict__ Xd,
   const int wu = __builtin_amdgcn_readfirstlane(w);  // wave-uniform copy of w
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
-    const int cid = wu + 8 * j;
-    const int c = cid < NCP ? cid : 0;
+    const int c = wu + 8 * j;  // < NCP
     const int panel = c / (4 * S), a = (c / 4) % S, quarter = c % 4;
     const int row = quarter * 16 + (l >> 2), part = (l & 3) ^ ((row >> 1) & 3);
     cpa[j] = a;
     voff[j] = ((panel ? t2 : t1) * 64 + row) * 64 + part * 16;
-    crow[j] = cid < NCP ? (panel * S + a) * 64 + quarter * 16 : 2 * S * 64;
+    crow[j] = (panel * S + a) * 64 + quarter * 16;
   }
   auto copy_step = [&](auto& L, int b, int ks) {
 #pragma unroll
