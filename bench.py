@@ -435,7 +435,10 @@ def controller_workload(args):
 
 
 def batched_workload(args):
-    """48 uneven screened instances: one-by-one builds vs the batched build."""
+    """48 uneven screened instances: one-by-one builds vs the batched build.
+
+    The instances are generated, screened and timed in groups whose dense B fit
+    in --batch-gb of device memory (largest first); the times add up."""
     import numpy as np
     import torch
     import dfinputs
@@ -443,39 +446,22 @@ def batched_workload(args):
 
     rng = np.random.default_rng(0)
     naos = [int(v) for v in 8 * rng.integers(16, args.batch_max_nao // 8 + 1, 48)]
+    s = args.slices
+    order = sorted(range(48), key=lambda i: -naos[i])
+    groups, cur, cur_b = [], [], 0.0
+    for i in order:
+        b = 8.0 * 4 * naos[i] ** 3 / 1e9
+        if cur and cur_b + b > args.batch_gb:
+            groups.append(cur)
+            cur, cur_b = [], 0.0
+        cur.append(i)
+        cur_b += b
+    groups.append(cur)
+    log(f"batched: 48 instances, nao {min(naos)}..{max(naos)}, {len(groups)} group(s) of at "
+        f"most {args.batch_gb:.0f} GB of B")
     ctx = Context()
     ctx.df_set_pblk(64)
-    insts = []
-    kept = []
-    log(f"batched: generating 48 instances, nao {min(naos)}..{max(naos)}")
-    for i, nao in enumerate(naos):
-        naux, nocc = 4 * nao, nao // 8
-        p = dfinputs.make_problem_device(nao=nao, naux=naux, nocc=nocc, L=12.0, seed=1000 + i)
-        nblk = nao // 8
-        mask = torch.empty((nblk, nblk), dtype=torch.uint8, device="cuda")
-        chunks = torch.empty(nao, dtype=torch.int64, device="cuda")
-        ctx.df_screen(p["B"], 8, 1e-10, mask, chunks)
-        kept.append(float(mask.float().mean()))
-        outs = dict(J=torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
-                    K=torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
-                    en=torch.empty(2, dtype=torch.float64, device="cuda"),
-                    eb=torch.empty(1, dtype=torch.float64, device="cuda"))
-        insts.append(dict(B=p["B"], C=p["C"], D=p["D"], mask=mask, chunks=chunks, **outs))
-    torch.cuda.synchronize()
-    s = args.slices
-    F = sum(flops_alg(i["B"].shape[1], i["B"].shape[0], i["C"].shape[1]) for i in insts)
-
-    def one_by_one():
-        for i in insts:
-            nao = i["B"].shape[1]
-            ctx.df_set_screening(i["mask"], i["chunks"], 8, nao)
-            ctx.df_build_jk(i["B"], None, i["C"], 2.0, i["D"], i["J"], i["K"], i["en"], i["eb"])
-        ctx.df_set_screening(None, None, 8, 0)
-
     ctx.df_set_precision(s)
-    need = max(ctx.df_workspace_size(i["B"].shape[0], i["B"].shape[1], i["C"].shape[1])
-               for i in insts)
-    ctx.df_set_workspace(torch.empty(need, dtype=torch.uint8, device="cuda"))
 
     def timed(fn, reps):
         fn()
@@ -489,26 +475,70 @@ def batched_workload(args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    ms_seq = timed(one_by_one, args.steps)
-    log(f"batched: one by one {ms_seq:.2f} ms")
-    # autotune every distinct shape (kept in the context for the batched run)
-    t0 = time.perf_counter()
-    for i in insts:
-        nao = i["B"].shape[1]
-        ctx.df_set_screening(i["mask"], i["chunks"], 8, nao)
-        ctx.df_autotune(i["B"], None, i["C"], 2.0, i["D"], i["J"], i["K"], i["en"], i["eb"], reps=2)
-    ctx.df_set_screening(None, None, 8, 0)
-    t_tune = time.perf_counter() - t0
-    probs = [ctx.make_problem(i["B"], i["C"], i["D"], i["J"], i["K"], i["en"], i["eb"], s,
-                              screen_mask=i["mask"], screen_chunks=i["chunks"]) for i in insts]
-    res = {}
-    for streams in (1, 4):
-        need = ctx.df_batched_workspace_size(probs, streams)
+    F = 0.0
+    kept = []
+    ms_seq = ms1 = ms4 = t_tune = 0.0
+    for g in groups:
+        insts = []
+        for i in g:
+            nao = naos[i]
+            naux, nocc = 4 * nao, nao // 8
+            p = dfinputs.make_problem_device(nao=nao, naux=naux, nocc=nocc, L=12.0, seed=1000 + i)
+            nblk = nao // 8
+            mask = torch.empty((nblk, nblk), dtype=torch.uint8, device="cuda")
+            chunks = torch.empty(nao, dtype=torch.int64, device="cuda")
+            ctx.df_screen(p["B"], 8, 1e-10, mask, chunks)
+            kept.append(float(mask.float().mean()))
+            outs = dict(J=torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+                        K=torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+                        en=torch.empty(2, dtype=torch.float64, device="cuda"),
+                        eb=torch.empty(1, dtype=torch.float64, device="cuda"))
+            insts.append(dict(B=p["B"], C=p["C"], D=p["D"], mask=mask, chunks=chunks, **outs))
+            del p
+        torch.cuda.synchronize()
+        F += sum(flops_alg(i["B"].shape[1], i["B"].shape[0], i["C"].shape[1]) for i in insts)
+
+        def one_by_one():
+            for i in insts:
+                nao = i["B"].shape[1]
+                ctx.df_set_screening(i["mask"], i["chunks"], 8, nao)
+                ctx.df_build_jk(i["B"], None, i["C"], 2.0, i["D"], i["J"], i["K"], i["en"],
+                                i["eb"])
+            ctx.df_set_screening(None, None, 8, 0)
+
+        need = max(ctx.df_workspace_size(i["B"].shape[0], i["B"].shape[1], i["C"].shape[1])
+                   for i in insts)
         ctx.df_set_workspace(None)
         ctx.df_set_workspace(torch.empty(need, dtype=torch.uint8, device="cuda"))
-        res[streams] = timed(lambda: ctx.df_build_jk_batched(probs, streams), args.steps)
-        log(f"batched: {streams} stream(s), tuned shapes: {res[streams]:.2f} ms")
-    ms = res[4]
+        ms_seq += timed(one_by_one, args.steps)
+        # autotune every distinct shape (kept in the context for the batched run)
+        t0 = time.perf_counter()
+        for i in insts:
+            nao = i["B"].shape[1]
+            ctx.df_set_screening(i["mask"], i["chunks"], 8, nao)
+            ctx.df_autotune(i["B"], None, i["C"], 2.0, i["D"], i["J"], i["K"], i["en"], i["eb"],
+                            reps=2)
+        ctx.df_set_screening(None, None, 8, 0)
+        t_tune += time.perf_counter() - t0
+        probs = [ctx.make_problem(i["B"], i["C"], i["D"], i["J"], i["K"], i["en"], i["eb"], s,
+                                  screen_mask=i["mask"], screen_chunks=i["chunks"]) for i in insts]
+        for streams in (1, 4):
+            need = ctx.df_batched_workspace_size(probs, streams)
+            ctx.df_set_workspace(None)
+            ctx.df_set_workspace(torch.empty(need, dtype=torch.uint8, device="cuda"))
+            ms = timed(lambda: ctx.df_build_jk_batched(probs, streams), args.steps)
+            if streams == 1:
+                ms1 += ms
+            else:
+                ms4 += ms
+        lo, hi = min(naos[i] for i in g), max(naos[i] for i in g)
+        log(f"batched: group of {len(insts)} (nao {lo}..{hi}): one by one {ms_seq:.1f}, "
+            f"1 stream {ms1:.1f}, 4 streams {ms4:.1f} ms so far")
+        del probs, insts
+        ctx.df_set_workspace(None)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    ms = ms4
     out = {"metric": METRIC, "value": F / ms / 1e9, "unit": "TFLOP/s", "n_gpus": 1,
            "steps": args.steps, "warmup": 1, "ms_per_step": ms, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
@@ -516,11 +546,13 @@ def batched_workload(args):
            "data": "synthetic",
            "config": {"workload": f"48 uneven instances, nao 8Z in [128, {args.batch_max_nao}], "
                                   "naux 4 nao, nocc nao/8, L 12, shell blocks of 8 screened at "
-                                  "1e-10", "slices": s, "naos": naos},
-           "one_by_one_ms": ms_seq, "batched_1stream_tuned_ms": res[1],
-           "batched_4streams_tuned_ms": res[4], "speedup_vs_one_by_one": ms_seq / ms,
+                                  f"1e-10, timed in {len(groups)} group(s) of at most "
+                                  f"{args.batch_gb:.0f} GB of dense B", "slices": s,
+                      "naos": naos},
+           "one_by_one_ms": ms_seq, "batched_1stream_tuned_ms": ms1,
+           "batched_4streams_tuned_ms": ms4, "speedup_vs_one_by_one": ms_seq / ms,
            "autotune_seconds": t_tune, "kept_block_fraction_mean": float(np.mean(kept)),
-           "flops_alg_total": F}
+           "kept_block_fraction_min": float(np.min(kept)), "flops_alg_total": F}
     ctx.close()
     return out
 
@@ -560,7 +592,9 @@ def main():
     ap.add_argument("--ctl-slack", type=float, default=1.0,
                     help="allocation budget as a multiple of the reference count's predicted error")
     ap.add_argument("--batch-max-nao", type=int, default=512,
-                    help="largest nao of the batched instances")
+                    help="largest nao of the batched instances (1200: the full range)")
+    ap.add_argument("--batch-gb", type=float, default=150.0,
+                    help="device memory for the dense B of one group of batched instances")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (scales HBM byte counters)")
     args = ap.parse_args()

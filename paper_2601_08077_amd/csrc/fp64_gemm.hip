@@ -79,16 +79,24 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
 #pragma unroll
   for (int f = 0; f < NF; ++f) acc[f] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  double va[4], vc[NF];
-  int kind = 0;  // PK: 0 below the tile's rows, 1 across the diagonal, 2 above (mirrored)
-  auto load = [&](int k0) {
+  // Register sets of one 16-k chunk: B values, C values, D values of the row
+  // dots, and (PK) the chunk's kind.  Two sets: the loads of chunk c + 2 are
+  // issued while chunk c is multiplied, so every load has two chunks of
+  // MFMAs to land (the D values travel with the chunk, so that no later load
+  // is waited on before them).
+  struct Regs {
+    double va[4], vc[NF], vd[4];
+    int kind;  // PK: 0 below the tile's rows, 1 across the diagonal, 2 above (mirrored)
+  };
+  auto load = [&](Regs& R, int k0) {
+    double* va = R.va;
     if constexpr (PK) {
-      kind = k0 + 16 <= mu0 ? 0 : (k0 >= mu0 + 64 ? 2 : 1);
-      if (kind == 0) {
+      R.kind = k0 + 16 <= mu0 ? 0 : (k0 >= mu0 + 64 ? 2 : 1);
+      if (R.kind == 0) {
         const double2 p0 = *reinterpret_cast<const double2*>(brow + k0 + lk);
         const double2 p1 = *reinterpret_cast<const double2*>(brow + k0 + lk + 2);
         va[0] = p0.x; va[1] = p0.y; va[2] = p1.x; va[3] = p1.y;
-      } else if (kind == 2) {
+      } else if (R.kind == 2) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int nu = min(k0 + lkT + j, nao - 1);
@@ -117,59 +125,66 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
       const int idx = t + 256 * j;
       const int kr = idx / NT, cc = idx - kr * NT;
       const int kk = k0 + kr, col = n0 + cc;
-      vc[j] = (kk < K && col < nocc) ? C[(int64_t)kk * nocc + col] : 0.0;
+      R.vc[j] = (kk < K && col < nocc) ? C[(int64_t)kk * nocc + col] : 0.0;
+    }
+    // D values of the row dots (PK: not needed past the diagonal)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kk = k0 + lk + j;
+      R.vd[j] = (drow && row_ok && kk < K && !(PK && R.kind == 2)) ? drow[kk] : 0.0;
     }
   };
   // Screened B: only the 64-wide nu chunks that meet a kept block in some row
   // of this tile are visited, 16 k at a time.
   const unsigned long long live = cmask ? tile_chunks<1>(cmask, m0, M, nao, w, l) : 0ull;
-  int k0 = cmask ? 64 * first_bit(live) : 0;
-  if (k0 < 0 || k0 >= K) k0 = -1;
-  if (k0 >= 0) load(k0);
-  int buf = 0;
-  while (k0 >= 0) {
-    int kn = k0 + 16;
+  auto next_of = [&](int k) {
+    if (k < 0) return -1;
+    int kn = k + 16;
     if (cmask && kn % 64 == 0) {
-      const int c = next_bit(live, k0 / 64);
+      const int c = next_bit(live, k / 64);
       kn = c >= 0 ? 64 * c : -1;
     }
-    if (kn >= K) kn = -1;
-    if (PK && kind == 2) {
+    return kn >= K ? -1 : kn;
+  };
+  int buf = 0;
+  // one chunk: chunk k0 (in registers cur) into LDS stage buf, its row dots,
+  // the barrier, the loads of the chunk after k1 (the one in flight in nx)
+  // into cur, then the MFMAs of stage buf
+  auto step = [&](Regs& cur, int& k0, int& k1) {
+    if (PK && cur.kind == 2) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) As[buf][lrT][lkT + j] = k0 + lkT + j < nao ? va[j] : 0.0;
+      for (int j = 0; j < 4; ++j) As[buf][lrT][lkT + j] = k0 + lkT + j < nao ? cur.va[j] : 0.0;
     } else if (PK) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) As[buf][lr][lk + j] = k0 + lk + j < nao ? va[j] : 0.0;
+      for (int j = 0; j < 4; ++j) As[buf][lr][lk + j] = k0 + lk + j < nao ? cur.va[j] : 0.0;
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) As[buf][lr][lk + j] = va[j];
+      for (int j = 0; j < 4; ++j) As[buf][lr][lk + j] = cur.va[j];
     }
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
       const int idx = t + 256 * j;
       const int kr = idx / NT, cc = idx - kr * NT;
-      Cs[buf][kr][cc] = vc[j];
+      Cs[buf][kr][cc] = cur.vc[j];
     }
     if (drow && row_ok) {
       if constexpr (PK) {
-        if (kind != 2) {
+        if (cur.kind != 2) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int kk = k0 + lk + j;
             const double wgt = kk < mu0 + lr ? 2.0 : (kk == mu0 + lr ? 1.0 : 0.0);
-            if (kk < K) rd = fma(va[j] * wgt, drow[kk], rd);
+            rd = fma(cur.va[j] * wgt, cur.vd[j], rd);
           }
         }
       } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int kk = k0 + lk + j;
-          if (kk < K) rd = fma(va[j], drow[kk], rd);
-        }
+        for (int j = 0; j < 4; ++j) rd = fma(cur.va[j], cur.vd[j], rd);
       }
     }
     __syncthreads();
-    if (kn >= 0) load(kn);
+    const int k2 = next_of(k1);
+    if (k2 >= 0) load(cur, k2);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const double a = As[buf][w * 16 + (l & 15)][kk * 4 + (l >> 4)];
@@ -177,8 +192,20 @@ __global__ __launch_bounds__(256) void k_x_fp64(const double* __restrict__ B, in
       for (int f = 0; f < NF; ++f)
         acc[f] = mfma_f64(a, Cs[buf][kk * 4 + (l >> 4)][f * 16 + (l & 15)], acc[f]);
     }
-    k0 = kn;
     buf ^= 1;
+    k0 = k1;
+    k1 = k2;
+  };
+  Regs r0, r1;
+  int k0 = cmask ? 64 * first_bit(live) : 0;
+  if (k0 < 0 || k0 >= K) k0 = -1;
+  int k1 = next_of(k0);
+  if (k0 >= 0) load(r0, k0);
+  if (k1 >= 0) load(r1, k1);
+  while (k0 >= 0) {
+    step(r0, k0, k1);
+    if (k0 < 0) break;
+    step(r1, k0, k1);
   }
 
   if (rowdot) {
@@ -250,51 +277,90 @@ __global__ __launch_bounds__(256) void k_k_fp64(const double* __restrict__ Xb, i
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  double va[4], vb[4];
-  auto load = [&](int b, int k0) {
-    const int64_t p0 = (int64_t)b * pblk;
-    const int kb = (int)(((p0 + pblk < naux ? p0 + pblk : naux) - p0) * nocc);
-    const double* xa = Xb + ((int64_t)b * nao + mu_ld) * kfull;
-    const double* xb = Xb + ((int64_t)b * nao + nu_ld) * kfull;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + li + j;
-      va[j] = (mu_ld < nao && k < kb) ? xa[k] : 0.0;
-      vb[j] = (nu_ld < nao && k < kb) ? xb[k] : 0.0;
-    }
+  // Two register sets of one 16-k chunk (4 values of row mu and of row nu per
+  // thread): the loads of chunk c + 2 are issued while chunk c is multiplied.
+  struct Regs {
+    double va[4], vb[4];
   };
-  // flattened (block, k chunk) steps
-  int b = b_lo, k0 = 0;
   auto kb_of = [&](int bb) {
     const int64_t p0 = (int64_t)bb * pblk;
     return (int)(((p0 + pblk < naux ? p0 + pblk : naux) - p0) * nocc);
   };
-  if (b < b_hi) load(b, 0);
+  auto load = [&](Regs& R, int b, int k0) {
+    const int kb = kb_of(b);
+    const double* xa = Xb + ((int64_t)b * nao + mu_ld) * kfull;
+    const double* xb = Xb + ((int64_t)b * nao + nu_ld) * kfull;
+    const int k = k0 + li;
+    if (k + 4 <= kb && (kfull & 1) == 0) {  // 16-byte loads (rows start at even elements)
+      if (mu_ld < nao) {
+        const double2 p0 = *reinterpret_cast<const double2*>(xa + k);
+        const double2 p1 = *reinterpret_cast<const double2*>(xa + k + 2);
+        R.va[0] = p0.x; R.va[1] = p0.y; R.va[2] = p1.x; R.va[3] = p1.y;
+      } else {
+        R.va[0] = R.va[1] = R.va[2] = R.va[3] = 0.0;
+      }
+      if (nu_ld < nao) {
+        const double2 p0 = *reinterpret_cast<const double2*>(xb + k);
+        const double2 p1 = *reinterpret_cast<const double2*>(xb + k + 2);
+        R.vb[0] = p0.x; R.vb[1] = p0.y; R.vb[2] = p1.x; R.vb[3] = p1.y;
+      } else {
+        R.vb[0] = R.vb[1] = R.vb[2] = R.vb[3] = 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        R.va[j] = (mu_ld < nao && k + j < kb) ? xa[k + j] : 0.0;
+        R.vb[j] = (nu_ld < nao && k + j < kb) ? xb[k + j] : 0.0;
+      }
+    }
+  };
+  // flattened (block, k chunk) steps
+  auto next_of = [&](int& b, int& k0) {
+    if (b >= b_hi) return;
+    k0 += 16;
+    if (k0 >= kb_of(b)) {
+      ++b;
+      k0 = 0;
+    }
+  };
   int buf = 0;
-  while (b < b_hi) {
+  auto step = [&](Regs& cur, int& b, int& k0, int& b1, int& k1) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      As[buf][lr][li + j] = va[j];
-      Bs[buf][lr][li + j] = vb[j];
+      As[buf][lr][li + j] = cur.va[j];
+      Bs[buf][lr][li + j] = cur.vb[j];
     }
     __syncthreads();
-    int nb2 = b, nk0 = k0 + 16;
-    if (nk0 >= kb_of(b)) { ++nb2; nk0 = 0; }
-    if (nb2 < b_hi) load(nb2, nk0);
+    int b2 = b1, k2 = k1;
+    next_of(b2, k2);
+    if (b2 < b_hi) load(cur, b2, k2);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const double a0 = As[buf][wr + (l & 15)][kk * 4 + (l >> 4)];
       const double a1 = As[buf][wr + 16 + (l & 15)][kk * 4 + (l >> 4)];
       const double b0 = Bs[buf][wc + (l & 15)][kk * 4 + (l >> 4)];
-      const double b1 = Bs[buf][wc + 16 + (l & 15)][kk * 4 + (l >> 4)];
+      const double b1v = Bs[buf][wc + 16 + (l & 15)][kk * 4 + (l >> 4)];
       acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
-      acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+      acc[0][1] = mfma_f64(a0, b1v, acc[0][1]);
       acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
-      acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+      acc[1][1] = mfma_f64(a1, b1v, acc[1][1]);
     }
     buf ^= 1;
-    b = nb2;
-    k0 = nk0;
+    b = b1;
+    k0 = k1;
+    b1 = b2;
+    k1 = k2;
+  };
+  Regs r0, r1;
+  int b = b_lo, k0 = 0;
+  int b1 = b, k1 = k0;
+  next_of(b1, k1);
+  if (b < b_hi) load(r0, b, k0);
+  if (b1 < b_hi) load(r1, b1, k1);
+  while (b < b_hi) {
+    step(r0, b, k0, b1, k1);
+    if (b >= b_hi) break;
+    step(r1, b, k0, b1, k1);
   }
 
   double* out = Kp + (int64_t)grp * nao * nao;
