@@ -816,12 +816,19 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         out["workloads"] = {}
-        for name in ("scf", "adaptive", "batched"):
+        for name in ("scf", "adaptive", "batched", "controller"):
             log(f"workload {name}")
-            rec = workloads[name](args)
+            wargs = args
+            if name == "controller":
+                # a shorter run than --workload controller (20k samples, nao 1024)
+                wargs = argparse.Namespace(**vars(args))
+                wargs.ctl_samples = min(args.ctl_samples, 20000)
+                wargs.ctl_nao = 1024
+            rec = workloads[name](wargs)
             out["workloads"][name] = {k: v for k, v in rec.items() if k not in
-                                      ("iterations", "metric", "n_gpus", "higher_is_better",
-                                       "scaling", "vs_baseline", "data")}
+                                      ("iterations", "iterations_plain", "iterations_controller",
+                                       "metric", "n_gpus", "higher_is_better", "scaling",
+                                       "vs_baseline", "data")}
             torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
