@@ -344,7 +344,11 @@ int df_rule_slices(int level, int fp64_below_level);
  *   NULL (then A alone).  nseg = ceil(n / seglen) <= 2^19.  FP64.
  * df_x_block_stats: the same over the aux blocks of X left in the workspace by
  *   the last df_build_jk of this shape (blocked layout: one segment per block
- *   of pblk aux indices); out[nblocks][2].
+ *   of pblk aux indices); out[nblocks][2].  After an INT8 build (every block
+ *   at s >= 1) the values come from what the build recorded (the maxima of
+ *   its X pass, the squared sums written by its slicing of X, summed per
+ *   block in a fixed order) instead of a pass over X; the sums then differ
+ *   from a direct pass by rounding only.
  * df_controller_features: feat[nblocks][16] (FP32) of one iteration from
  *   bstats [nblocks][2] (df_block_stats of B per aux block), xstats
  *   [nblocks][2] (df_x_block_stats of the previous iteration), dstat[2]

@@ -262,7 +262,11 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
     rule (one uniform build at s_ref, no spot check) the first iteration,
     which has no previous X and K for its features, and every iteration whose
     allocation the cost table prices less than `min_gain` times the reference
-    count's cost below it (the controller's own work would eat the saving)."""
+    count's cost below it (the controller's own work would eat the saving).
+    With a cost table the controller also watches its own clock: once an
+    iteration it ran at some reference count (without a fallback) took longer
+    than the table's uniform build at that count, it leaves the later
+    iterations at that count to the plain rule."""
     import torch
     import dfinputs
     naux, nao = binding._shape(B, layout)
@@ -280,6 +284,7 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
     level, e_prev, e_prev2 = 4, None, None
     floor = np.zeros(8) if floor is None else np.asarray(floor, dtype=np.float64)
     corr = floor.copy()  # per-s correction of the predictions (decades, >= floor)
+    no_gain = set()  # reference counts at which a controlled iteration did not pay
     recs = []
     for k, C in enumerate(orbitals):
         corr = np.maximum(corr * decay, floor)
@@ -289,7 +294,7 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
         # allocation's host round trip, spot check, fallback, and the block
         # statistics of this iteration that the next one's features read)
         ev0.record()
-        plain = s_ref == 0 or k == 0
+        plain = s_ref == 0 or k == 0 or s_ref in no_gain
         fallback = False
         pred_h = None
         if not plain:
@@ -313,12 +318,13 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
             ctx.ensure_workspace(naux, nao, nocc)
             ctx.df_build_jk(B, b_exp, C, occ, b.D, b.J, b.K, b.en, b.eb, **kw)
             if spot > 0:
+                # absolute errors (kfro = 1) and ||K||_F^2 come back in one round trip
                 ctx.df_block_stats(b.K, b.kfro, b.K.numel())
-                kfro = math.sqrt(float(b.kfro.cpu()[0, 1]))
                 blocks = dfinputs.spot_blocks(nb, spot, k, seed)
+                ctx.df_spot_check(B, C, occ, 1.0, blocks, spot_err[:len(blocks)], **kw)
+                kfro = math.sqrt(float(b.kfro.cpu()[0, 1]))
                 if kfro > 0:
-                    ctx.df_spot_check(B, C, occ, kfro, blocks, spot_err[:len(blocks)], **kw)
-                    se = spot_err[:len(blocks)].cpu().numpy()
+                    se = spot_err[:len(blocks)].cpu().numpy() / kfro
                     err_pred = np.minimum.accumulate(10.0 ** pred_h.astype(np.float64), axis=1)
                     budget = slack * float(err_pred[:, s_ref - 1].sum())
                     excess = sum(max(0.0, float(se[i]) - float(err_pred[blk, sb[blk] - 1]))
@@ -337,6 +343,8 @@ def run_controlled(ctx, B, b_exp, orbitals, params, occ=2.0, pblk=64, fp64_below
         ev1.record()
         e_now = _energy(b.en)
         ms = ev0.elapsed_time(ev1)
+        if cost is not None and not plain and not fallback and ms > cost[s_ref - 1]:
+            no_gain.add(s_ref)
         rec = dict(iteration=k, level=level, s_ref=s_ref, slices=list(sb), fallback=fallback,
                    mode="plain" if plain else "controller",
                    correction=[round(float(v), 3) for v in corr],

@@ -217,6 +217,18 @@ def test_x_block_stats_after_build(torch_dev, ctx):
     for b, (p0, p1) in enumerate(em.block_ranges(naux, 64)):
         assert got[b, 0] == np.max(np.abs(X[p0:p1]))
         assert got[b, 1] == pytest.approx(np.sum(X[p0:p1] ** 2), rel=1e-12)
+    # a df_build_x in between overwrites the recorded maxima: the statistics
+    # then come from a pass over the workspace X, which still holds the X of
+    # the df_build_jk (df_build_x writes the caller's X only)
+    Xo = torch.empty((naux, nao, 7), dtype=torch.float64, device="cuda")
+    ctx.df_build_x(_dev(torch, 2.0 * p["B"]), None, _dev(torch, p["C"]), Xo)
+    out2 = torch.empty((3, 2), dtype=torch.float64, device="cuda")
+    ctx.df_x_block_stats(naux, nao, 7, out2)
+    torch.cuda.synchronize()
+    got2 = out2.cpu().numpy()
+    assert np.array_equal(got2[:, 0], got[:, 0])
+    for b, (p0, p1) in enumerate(em.block_ranges(naux, 64)):
+        assert got2[b, 1] == pytest.approx(np.sum(X[p0:p1] ** 2), rel=1e-12)
 
 
 def test_block_errors_and_spot_check(torch_dev, ctx):

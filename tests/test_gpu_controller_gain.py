@@ -73,3 +73,23 @@ def test_trained_controller_beats_plain_rule(torch_dev):
     assert abs(ctl[-1]["energy_err"]) <= 4.0 * abs(plain[-1]["energy_err"]) + 1e-12
     ctx.close()
 
+
+def test_trained_controller_beats_plain_rule_in_time(torch_dev):
+    """The controller benchmark's sequence at its shape (nao 1536, naux 6144,
+    nocc 192, 30 iterations) with a training set of about 20k samples: the
+    controlled run (features, prediction, per-block builds, FP64 spot checks
+    and any fallback rebuilds, all inside the timed region) takes less GPU
+    time than the plain rule's at the same reference counts, with a largest K
+    error no worse than the plain rule's."""
+    import argparse
+    import bench
+    args = argparse.Namespace(ctl_samples=20000, ctl_train_steps=8000, ctl_nao=1536,
+                              ctl_slack=0.5, ctl_min_gain=0.1)
+    out = bench.controller_workload(args)
+    print(f"time: controller {out['controller_total_ms']:.1f} ms vs plain "
+          f"{out['plain_total_ms']:.1f} ms ({out['speedup_vs_plain']:.3f}x); max K error "
+          f"{out['max_k_err_controller']:.2e} vs {out['max_k_err_plain']:.2e}; "
+          f"{out['controller_iterations']} controlled iterations, {out['fallbacks']} fallbacks")
+    assert out["controller_iterations"] > 0
+    assert out["controller_total_ms"] < out["plain_total_ms"]
+    assert out["max_k_err_controller"] <= out["max_k_err_plain"]
