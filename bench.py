@@ -560,6 +560,41 @@ def batched_workload(args):
     return out
 
 
+def library_fp64(Bd, C, D, reps):
+    """The FP64 build written with the vendor BLAS through torch (rocBLAS /
+    hipBLASLt) on dense B, as a reference for the FP64 MFMA kernels: X as one
+    GEMM over the stacked rows (P, mu), K = occ Z^T Z with Z the rows (P, i)
+    of X (one transposing copy, timed with K), rho and J as two GEMVs.  Median
+    stage times (ms) over `reps` builds after one warm-up."""
+    import torch
+    naux, nao, _ = Bd.shape
+    nocc = C.shape[1]
+    Bs = Bd.reshape(naux * nao, nao)
+    Bf = Bd.reshape(naux, nao * nao)
+
+    def once():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        X = Bs @ C
+        ev[1].record()
+        Z = X.reshape(naux, nao, nocc).permute(0, 2, 1).reshape(naux * nocc, nao).contiguous()
+        K = 2.0 * (Z.t() @ Z)
+        ev[2].record()
+        rho = Bf @ D.reshape(-1)
+        J = rho @ Bf
+        ev[3].record()
+        torch.cuda.synchronize()
+        del X, Z, K, J
+        return [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+
+    once()
+    ts = [once() for _ in range(max(reps, 1))]
+    med = [sorted(t[i] for t in ts)[len(ts) // 2] for i in range(3)]
+    return {"x_ms": med[0], "k_ms": med[1], "j_ms": med[2], "total_ms": sum(med),
+            "how": "torch.matmul in FP64 (rocBLAS / hipBLASLt): X = B C stacked, "
+                   "K = occ Z^T Z (Z = rows (P, i) of X, copy included), rho and J as GEMVs"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -662,6 +697,8 @@ def main():
         torch.cuda.synchronize()
         dense_rec["fp64_ms" if s_ == 0 else f"s{s_}_ms"] = e0.elapsed_time(e1) / args.sweep_reps
     log(f"dense B: {dense_rec}")
+    dense_rec["library_fp64"] = library_fp64(Bd, C, D, args.sweep_reps)
+    log(f"dense B, vendor BLAS FP64: {dense_rec['library_fp64']}")
     B = dfinputs.pack_lower(Bd)
     del Bd, p["B"]
     torch.cuda.synchronize()
@@ -707,8 +744,9 @@ def main():
     nK = float(torch.linalg.norm(K64))
     nJ = float(torch.linalg.norm(J64))
     log(f"FP64: {ms64:.3f} ms/step")
-    # speedups are quoted against the faster FP64 build of the two layouts
-    ms64_best = min(ms64, dense_rec["fp64_ms"])
+    # speedups are quoted against the fastest FP64 build measured: the FP64
+    # MFMA kernels on either layout or the vendor BLAS on dense B
+    ms64_best = min(ms64, dense_rec["fp64_ms"], dense_rec["library_fp64"]["total_ms"])
 
     sweep = []
     if not args.no_sweep:
@@ -798,8 +836,9 @@ def main():
         "fp64_mfma": {"ms_per_step": ms64, "eff_tflops": F / ms64 / 1e9,
                       "stages_ms": {k: round(v, 4) for k, v in st64.items()}},
         "speedup_vs_fp64": ms64_best / ms,
-        "speedup_vs_fp64_basis": "the faster FP64 MFMA build of packed and dense B "
-                                 f"({ms64_best:.3f} ms)",
+        "speedup_vs_fp64_basis": "the fastest FP64 build measured (FP64 MFMA kernels on "
+                                 "packed and dense B, vendor BLAS on dense B): "
+                                 f"{ms64_best:.3f} ms",
         "error": err,
         "stages_ms": {k: round(v, 4) for k, v in st.items()},
         "roofline": roof,
