@@ -44,6 +44,7 @@ SHAPES = [  # nao, naux, nocc, pblk (ragged nao and naux, one and several row ti
     (130, 66, 33, 64),
     (200, 30, 100, 16),
     (150, 24, 140, 64),              # 192 padded columns
+    (130, 40, 80, 64),               # 96 padded columns, ragged nao
 ]
 
 
