@@ -12,9 +12,9 @@ decision, and the per-s correction of the predictions.
 
 A prediction is log10(max |K_b(s) - K_b| / ||K||_F) for s = 1..8.  At each
 iteration the plain rule still names a reference count s_ref; the controller
-gives every block the count that keeps the predicted total error at or below
-that of s_ref everywhere, with the fewest digit products
-(df_controller_allocate).  Sampled blocks are recomputed in FP64
+gives every block the count that keeps the predicted total error within a
+budget tied to that of s_ref everywhere, at the lowest cost (a table of
+measured build times, or digit products; df_controller_allocate).  Sampled blocks are recomputed in FP64
 (df_spot_check).  Their excess over the prediction, scaled up to all blocks
 (nblocks / samples times the summed excess), estimates how far the whole
 build overshoots its predicted error; when that estimate exceeds `margin`
