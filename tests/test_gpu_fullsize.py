@@ -196,3 +196,23 @@ def test_fullsize_mixed_block_counts_sampled(full):
     assert np.array_equal(Kss, Kref)
     Kfp = jk.k_rows_fp64(full["Bsub"], C, occ=p["occ"])
     assert np.abs(Kss - Kfp).max() <= float(eb.cpu()[0])
+
+
+@pytest.mark.parametrize("s", [4, 6])
+def test_fullsize_extra_pairs_sampled(full, s):
+    """The extra digit-pair scheme (a + b <= s + 2) at the full size: X and K
+    restricted to the sample bit-exact against the oracle's scheme with
+    extra = 1, and K within the (tighter) stated bound of the FP64 K."""
+    p, ctx = full["p"], full["ctx"]
+    C = p["C_host"]
+    ctx.df_set_extra_pairs(1)
+    try:
+        got = _gpu(full, s)
+    finally:
+        ctx.df_set_extra_pairs(0)
+    X, _, _ = em.emulated_x(full["Bsub"], C, s, extra=1)
+    assert np.array_equal(got["Xs"], X)
+    K, _ = em.emulated_k(X, s, occ=p["occ"], pblk=64, groups=got["groups"], extra=1)
+    assert np.array_equal(got["Kss"], K)
+    Kfp = jk.k_rows_fp64(full["Bsub"], C, occ=p["occ"])
+    assert np.abs(got["Kss"] - Kfp).max() <= got["bound"]

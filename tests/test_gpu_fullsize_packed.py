@@ -73,3 +73,36 @@ def test_packed_1024_sampled_bit_exact(full, s):
     assert np.array_equal(Kss, Kref)
     Kfp = jk.k_rows_fp64(full["Bsub"], C, occ=p["occ"])
     assert np.abs(Kss - Kfp).max() <= float(eb.cpu()[0])
+
+
+def test_packed_1024_extra_pairs_sampled(full):
+    """The extra digit-pair scheme on packed B at this size (s = 5, extra = 1):
+    sampled X and K bit-exact against the oracle's scheme."""
+    import torch
+    p, ctx, kw = full["p"], full["ctx"], full["kw"]
+    nao, naux, nocc = SHAPE["nao"], SHAPE["naux"], SHAPE["nocc"]
+    s = 5
+    ctx.df_set_precision(s)
+    ctx.df_set_k_groups(0)
+    ctx.df_set_extra_pairs(1)
+    try:
+        J = torch.empty((nao, nao), dtype=torch.float64, device="cuda")
+        K = torch.empty_like(J)
+        en = torch.empty(2, dtype=torch.float64, device="cuda")
+        eb = torch.empty(1, dtype=torch.float64, device="cuda")
+        ctx.df_build_jk(full["Bp"], full["be"], p["C"], p["occ"], p["D"], J, K, en, eb, **kw)
+        X = torch.empty((naux, nao, nocc), dtype=torch.float64, device="cuda")
+        ctx.df_build_x(full["Bp"], full["be"], p["C"], X, **kw)
+        St = full["St"]
+        Xs = X.index_select(1, St).cpu().numpy()
+        del X
+        torch.cuda.synchronize()
+        assert ctx.df_get_status() == 0
+        Kss = K.index_select(0, St).index_select(1, St).cpu().numpy()
+        groups = ctx.df_get_k_groups()
+    finally:
+        ctx.df_set_extra_pairs(0)
+    Xref, _, _ = em.emulated_x(full["Bsub"], p["C_host"], s, extra=1)
+    assert np.array_equal(Xs, Xref)
+    Kref, _ = em.emulated_k(Xref, s, occ=p["occ"], pblk=64, groups=groups, extra=1)
+    assert np.array_equal(Kss, Kref)
