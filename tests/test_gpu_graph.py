@@ -62,3 +62,60 @@ def test_build_jk_graph_replays(packed, s):
     assert ctx.df_get_status() == 0
     del g
     ctx.close()
+
+
+@pytest.mark.parametrize("streams", [1, 4])
+def test_batched_build_graph_replays(streams):
+    """The batched build (uneven instances, mixed slice counts, some screened)
+    captured with its worker streams (forked and joined by events inside the
+    capture) and replayed: every replay equals the eager batched build."""
+    import torch
+    from paper_2601_08077_amd import Context
+    st = torch.cuda.Stream()
+    ctx = Context(stream=st)
+    rng = np.random.default_rng(4)
+    with torch.cuda.stream(st):
+        ctx.df_set_pblk(64)
+        ctx.df_set_k_groups(0)
+        insts = []
+        for i in range(7):
+            nao = int(rng.integers(4, 25)) * 8
+            naux, nocc = 4 * nao, max(1, nao // 8)
+            p = dfinputs.make_problem(nao=nao, naux=naux, nocc=nocc, L=6.0, seed=200 + i)
+            inst = dict(B=torch.from_numpy(p["B"]).cuda(), C=torch.from_numpy(p["C"]).cuda(),
+                        D=torch.from_numpy(p["D"]).cuda(), mask=None, chunks=None,
+                        J=torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+                        K=torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+                        en=torch.empty(2, dtype=torch.float64, device="cuda"),
+                        eb=torch.empty(1, dtype=torch.float64, device="cuda"),
+                        slices=int(rng.choice([0, 3, 5, 7])))
+            if i % 3 == 0:
+                nblk = nao // 8
+                inst["mask"] = torch.empty((nblk, nblk), dtype=torch.uint8, device="cuda")
+                inst["chunks"] = torch.empty(nao, dtype=torch.int64, device="cuda")
+                ctx.df_screen(inst["B"], 8, 1e-6, inst["mask"], inst["chunks"])
+            insts.append(inst)
+        probs = [ctx.make_problem(i["B"], i["C"], i["D"], i["J"], i["K"], i["en"], i["eb"],
+                                  i["slices"], screen_mask=i["mask"], screen_chunks=i["chunks"])
+                 for i in insts]
+        need = ctx.df_batched_workspace_size(probs, streams)
+        ctx.df_set_workspace(torch.empty(need, dtype=torch.uint8, device="cuda"))
+        ctx.df_build_jk_batched(probs, streams)  # creates the worker streams and events
+        st.synchronize()
+        assert ctx.df_get_status() == 0
+        ref = [[i[k].clone() for k in ("J", "K", "en", "eb")] for i in insts]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st):
+            ctx.df_build_jk_batched(probs, streams)
+        for rep in range(3):
+            for i in insts:
+                for k in ("J", "K", "en", "eb"):
+                    i[k].fill_(-1.0)
+            g.replay()
+            st.synchronize()
+            for i, r in zip(insts, ref):
+                for k, v in zip(("J", "K", "en", "eb"), r):
+                    assert torch.equal(i[k], v), (rep, k)
+    assert ctx.df_get_status() == 0
+    del g
+    ctx.close()
