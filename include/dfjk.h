@@ -39,6 +39,12 @@
  *     Data errors found on the device (a NaN or Inf in a sliced operand) set
  *     a status word that df_get_status() reads (it synchronises the stream).
  *   - One context per stream; a context is not thread-safe.
+ *   - HIP graphs: df_density, df_build_x, df_build_jk and df_build_jk_batched
+ *     enqueue kernels (and, batched, event records and waits that fork and
+ *     join its worker streams) and nothing else: no memset, allocation or
+ *     synchronisation.  They may be captured in a graph on the context stream;
+ *     the batched build once a first eager call has created its worker
+ *     streams.  Replays read and write the buffers given at capture.
  */
 #ifndef DFJK_H
 #define DFJK_H

@@ -1,7 +1,7 @@
 """The J/K build captured in a HIP graph (torch.cuda.CUDAGraph on the
 context's stream) and replayed: every replay, on new orbitals copied into the
 captured input buffers between the replays, gives the eager build of the same
-inputs bit for bit (density, X, K, rho, J, energies and the error bound), on
+inputs bit for bit (density, X, K, J, energies and the error bound), on
 dense and packed B, in FP64 and at two slice counts."""
 import numpy as np
 import pytest
@@ -33,6 +33,7 @@ def test_build_jk_graph_replays(packed, s):
         J, K = torch.empty_like(D), torch.empty_like(D)
         en = torch.empty(2, dtype=torch.float64, device="cuda")
         eb = torch.empty(1, dtype=torch.float64, device="cuda")
+        X = torch.empty((naux, nao, nocc), dtype=torch.float64, device="cuda")
         ctx.df_set_precision(s)
         ctx.df_set_pblk(64)
         ctx.ensure_workspace(naux, nao, nocc)
@@ -41,12 +42,14 @@ def test_build_jk_graph_replays(packed, s):
         def build():
             ctx.df_density(C, 2.0, D)
             ctx.df_build_jk(B, be, C, 2.0, D, J, K, en, eb, **kw)
+            ctx.df_build_x(B, be, C, X, **kw)
 
+        outs = (D, J, K, en, eb, X)
         refs = []
         for Ck in orbs:
             C.copy_(torch.from_numpy(Ck))
             build()
-            refs.append([t.clone() for t in (D, J, K, en, eb)])
+            refs.append([t.clone() for t in outs])
         st.synchronize()
         assert ctx.df_get_status() == 0
         g = torch.cuda.CUDAGraph()
@@ -57,7 +60,7 @@ def test_build_jk_graph_replays(packed, s):
                 C.copy_(torch.from_numpy(Ck))
                 g.replay()
                 st.synchronize()
-                for got, ref in zip((D, J, K, en, eb), refs[k]):
+                for got, ref in zip(outs, refs[k]):
                     assert torch.equal(got, ref), (rep, k)
     assert ctx.df_get_status() == 0
     del g
