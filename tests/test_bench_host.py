@@ -73,3 +73,15 @@ def test_traffic_record_used_only_while_sources_unchanged(tmp_path):
     assert b.measured_traffic("k", 7) is None      # another stage
     src.write_text("// kernel v2\n")               # the kernel changed since
     assert b.measured_traffic("x", 7) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and says so
+    (before touching torch or the GPU)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
