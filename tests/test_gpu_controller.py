@@ -272,3 +272,37 @@ def test_block_errors_and_spot_check(torch_dev, ctx):
             assert np.allclose(e, ref, rtol=1e-6, atol=1e-16)
     finally:
         ctx.df_set_block_precision(None)
+
+
+def test_controller_clock_leaves_unprofitable_counts_to_the_plain_rule(torch_dev):
+    """run_controlled with a cost table that prices every count at almost
+    nothing: each controlled iteration then takes longer than the table's
+    uniform build at its reference count, so after the first one at a count
+    (without fallback; no spot checks here) every later iteration at that
+    count runs the plain build."""
+    torch = torch_dev
+    from paper_2601_08077_amd import Context, controller
+    nao, naux, nocc, n_iter = 96, 256, 12, 8
+    p = dfinputs.make_problem(nao=nao, naux=naux, nocc=nocc, L=8.0, seed=21, block_scale=4)
+    orbs = [torch.from_numpy(c).cuda()
+            for c in dfinputs.perturbed_orbitals(p["C"], n_iter, seed=21)]
+    B = torch.from_numpy(p["B"]).cuda()
+    c = Context()
+    be = torch.empty(naux * nao, dtype=torch.int32, device="cuda")
+    c.df_b_exponents(B, be)
+    params = torch.from_numpy(dfinputs.mlp_init(3)).cuda()
+    s_refs = [3, 3, 3, 4, 4, 4, 5, 5]
+    recs = controller.run_controlled(c, B, be, orbs, params, s_refs=s_refs, spot=0,
+                                     cost=[1e-9] * 8, min_gain=0.0)
+    c.close()
+    seen = set()
+    for r in recs:
+        assert r["s_ref"] == s_refs[r["iteration"]]
+        if r["iteration"] == 0:
+            assert r["mode"] == "plain"
+        elif r["s_ref"] in seen:
+            assert r["mode"] == "plain" and r["slices"] == [r["s_ref"]] * (naux // 64)
+        else:
+            assert r["mode"] == "controller" and not r["fallback"]
+            seen.add(r["s_ref"])
+    assert seen == {3, 4, 5}
